@@ -1,0 +1,33 @@
+"""Plain FP64 CPU oracle for the HiGP on-the-fly kernel MatVec path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call or
+link anything under ``oracle/``; only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code with the HIP path.
+
+Every function forms the regularised kernel matrix densely (one row block at a
+time), in float64, with direct coordinate differences, and then multiplies.  It
+follows the paper's statement of the problem ("Gaussian Processes" section):
+
+* ``K̂ = f²·k(X, X; l) + s·I`` with Θ = (s, f, l);
+* the negative log marginal likelihood and its gradient;
+* PCG for ``K̂⁻¹y`` with a preconditioner ``M ≈ K̂``;
+* eq. (1) (log-determinant split) with stochastic Lanczos quadrature;
+* eq. (2) (trace split) with the Hutchinson estimator.
+
+Parity status of each function is stated in its docstring.  Functions whose
+result has no pin other than itself say "parity unpinned".
+"""
+from .kernels import (GAUSSIAN, MATERN32, sqdist, kernel_value, kernel_dl,
+                      khat_dense, khat_block)
+from .matvec import kmatvec, kmatvec_grad, kmatvec_bf16_emulated, round_bf16
+from .solvers import (pcg, lanczos, tridiag_eig, slq_logdet, slq_from_tridiag)
+from .gp import (nlml_exact, nlml_grad_exact, nlml_grad_hutchinson,
+                 logdet_exact)
+
+__all__ = [
+    "GAUSSIAN", "MATERN32", "sqdist", "kernel_value", "kernel_dl", "khat_dense",
+    "khat_block", "kmatvec", "kmatvec_grad", "kmatvec_bf16_emulated",
+    "round_bf16", "pcg", "lanczos", "tridiag_eig", "slq_logdet",
+    "slq_from_tridiag", "nlml_exact", "nlml_grad_exact",
+    "nlml_grad_hutchinson", "logdet_exact",
+]

@@ -1,0 +1,176 @@
+"""PCG, Lanczos and stochastic Lanczos quadrature (oracle, FP64).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+* PCG follows the preconditioned conjugate gradient method the paper cites
+  (Saad 2003, Alg. 9.1) for ``K̂⁻¹y`` with ``M ≈ K̂`` ("Gaussian Processes"
+  section).  Several right-hand sides are k independent recurrences that share
+  one k-column MatVec; each column stops on its own when its recursively
+  updated residual satisfies ‖r‖₂/‖b‖₂ ≤ tol (checked after every iteration)
+  and is then frozen.
+* SLQ estimates the second term of eq. (1), log|M^{-1/2} K̂ M^{-1/2}|, with
+  the stochastic Lanczos quadrature of Ubaru et al. (2017): Lanczos from
+  z/‖z‖, eigen-decomposition T = S Θ Sᵀ, and ‖z‖² Σ_k S_{1k}² log θ_k per
+  probe, averaged over probes.
+"""
+import numpy as np
+import scipy.linalg
+
+
+def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
+        true_matvec=None):
+    """Solve A X = B column by column with (Jacobi-)preconditioned CG.
+
+    matvec(P) -> A·P for an n×k block.  mdiag: diagonal of M (None = no
+    preconditioner).  refine_every = R > 0 replaces the recursive residual by
+    the true residual b − A·x (computed with ``true_matvec``, default
+    ``matvec``) after every R-th iteration of a column.
+
+    Returns (X, iters, relres, converged) with per-column arrays; relres is the
+    recursive relative residual at exit.
+    """
+    B = np.asarray(B, dtype=np.float64)
+    vec = B.ndim == 1
+    B = B[:, None] if vec else B
+    n, k = B.shape
+    tmv = true_matvec if true_matvec is not None else matvec
+    minv = None if mdiag is None else 1.0 / np.asarray(mdiag, dtype=np.float64)
+
+    def prec(R):
+        return R.copy() if minv is None else minv[:, None] * R
+
+    X = np.zeros((n, k)) if x0 is None else np.array(x0, dtype=np.float64).reshape(n, k)
+    R = B - matvec(X) if x0 is not None else B.copy()
+    bnorm = np.linalg.norm(B, axis=0)
+    Z = prec(R)
+    P = Z.copy()
+    rho = np.sum(R * Z, axis=0)
+    iters = np.zeros(k, dtype=np.int64)
+    relres = np.where(bnorm > 0, np.linalg.norm(R, axis=0) / np.where(bnorm > 0, bnorm, 1.0), 0.0)
+    active = relres > tol
+    for _ in range(max_iter):
+        if not active.any():
+            break
+        Q = matvec(P)
+        a = active
+        alpha = rho[a] / np.sum(P[:, a] * Q[:, a], axis=0)
+        X[:, a] += alpha * P[:, a]
+        R[:, a] -= alpha * Q[:, a]
+        iters[a] += 1
+        if refine_every > 0:
+            due = a & (iters % refine_every == 0)
+            if due.any():
+                R[:, due] = B[:, due] - tmv(X)[:, due]
+        relres[a] = np.linalg.norm(R[:, a], axis=0) / bnorm[a]
+        done = a & (relres <= tol)
+        active = a & ~done
+        a = active
+        if not a.any():
+            break
+        Z = prec(R)
+        rho_new = np.sum(R[:, a] * Z[:, a], axis=0)
+        beta = rho_new / rho[a]
+        rho[a] = rho_new
+        P[:, a] = Z[:, a] + beta * P[:, a]
+    converged = relres <= tol
+    if vec:
+        return X[:, 0], iters[0], relres[0], bool(converged[0])
+    return X, iters, relres, converged
+
+
+def lanczos(matvec, Z, m, reorth=True, breakdown=1e-12):
+    """Lanczos tridiagonalisation from each column of Z (n×N), independently.
+
+    Step j (0-based) of column c: w = A q_j; α_j = q_jᵀw;
+    w ← w − α_j q_j − β_{j−1} q_{j−1}; with ``reorth`` one classical
+    Gram–Schmidt pass of w against all of q_0..q_j; β_j = ‖w‖.  The column
+    stops after m steps, or early (breakdown) when β_j ≤ breakdown·max|α_0..j|,
+    in which case its T has size j+1.  matvec is applied to the n×N block.
+
+    Returns (alphas, betas): lists (one per column) of 1-D arrays of lengths
+    m_c and m_c − 1.
+    """
+    Z = np.asarray(Z, dtype=np.float64)
+    if Z.ndim == 1:
+        Z = Z[:, None]
+    n, N = Z.shape
+    q = Z / np.linalg.norm(Z, axis=0)
+    Qs = [q.copy()]
+    q_prev = np.zeros_like(q)
+    beta_prev = np.zeros(N)
+    alphas = [[] for _ in range(N)]
+    betas = [[] for _ in range(N)]
+    live = np.ones(N, dtype=bool)
+    amax = np.zeros(N)
+    for j in range(m):
+        W = matvec(q)
+        alpha = np.sum(q * W, axis=0)
+        W = W - alpha * q - beta_prev * q_prev
+        if reorth:
+            Qj = np.stack(Qs, axis=0)                    # (j+1)×n×N
+            coef = np.einsum('jnc,nc->jc', Qj, W)
+            W = W - np.einsum('jnc,jc->nc', Qj, coef)
+        beta = np.linalg.norm(W, axis=0)
+        amax = np.maximum(amax, np.abs(alpha))
+        for c in range(N):
+            if live[c]:
+                alphas[c].append(alpha[c])
+        if j == m - 1:
+            break
+        stop = live & (beta <= breakdown * amax)
+        for c in range(N):
+            if live[c] and not stop[c]:
+                betas[c].append(beta[c])
+        live = live & ~stop
+        if not live.any():
+            break
+        safe = np.where(live, beta, 1.0)
+        q_next = np.where(live, W / safe, 0.0)
+        q_prev, q = q, q_next
+        beta_prev = np.where(live, beta, 0.0)
+        Qs.append(q.copy())
+    return ([np.array(a) for a in alphas], [np.array(b) for b in betas])
+
+
+def tridiag_eig(alpha, beta):
+    """Eigenvalues θ and first eigenvector components τ of the symmetric
+    tridiagonal T with diagonal alpha and off-diagonal beta (LAPACK via SciPy)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    if alpha.size == 1:
+        return alpha.copy(), np.ones(1)
+    theta, S = scipy.linalg.eigh_tridiagonal(alpha, beta)
+    return theta, S[0, :]
+
+
+def slq_from_tridiag(alpha, beta, znorm2):
+    """One probe's quadrature: ‖z‖² Σ_k τ_k² log θ_k."""
+    theta, tau = tridiag_eig(alpha, beta)
+    return znorm2 * np.sum(tau * tau * np.log(theta))
+
+
+def slq_logdet(matvec, Z, m, reorth=True, mdiag=None):
+    """Estimate log|A| by eq. (1) with M = diag(mdiag) (None: M = I) and SLQ
+    on M^{-1/2} A M^{-1/2} with the probe columns of Z.
+
+    Returns (logdet, per_probe) where per_probe[i] = log|M| + the i-th probe's
+    quadrature, so that logdet = mean(per_probe).
+    """
+    Z = np.asarray(Z, dtype=np.float64)
+    if Z.ndim == 1:
+        Z = Z[:, None]
+    if mdiag is None:
+        op = matvec
+        logm = 0.0
+    else:
+        d = np.asarray(mdiag, dtype=np.float64)
+        isq = 1.0 / np.sqrt(d)
+        logm = float(np.sum(np.log(d)))
+
+        def op(Q):
+            return isq[:, None] * matvec(isq[:, None] * Q)
+    alphas, betas = lanczos(op, Z, m, reorth=reorth)
+    zn2 = np.sum(Z * Z, axis=0)
+    per = np.array([logm + slq_from_tridiag(a, b, zn2[c])
+                    for c, (a, b) in enumerate(zip(alphas, betas))])
+    return float(np.mean(per)), per
