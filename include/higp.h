@@ -1,0 +1,167 @@
+/*
+ * higp.h — C ABI of the MI355X (gfx950) on-the-fly kernel MatVec engine.
+ *
+ * The operations follow the statement of the Gaussian-process problem in
+ * HiGP (Huang, Xu, Xi, Chow; arXiv 2503.02259), section "Gaussian
+ * Processes": training points X ∈ R^{n×d}, parameters Θ = (s, f, l) (noise
+ * level s, scale f, kernel parameter l) and the regularised kernel matrix
+ *
+ *        K̂ = f² · k(X, X; l) + s · I.
+ *
+ * The kernels k are the Gaussian (RBF) and Matérn-3/2 kernels named in the
+ * paper's Listing 1 and Tables 1-2, in their textbook form with a scalar,
+ * isotropic length-scale l and r = ‖x_i − x_j‖₂:
+ *
+ *        Gaussian     k(r) = exp(−r² / (2 l²))
+ *        Matérn-3/2   k(r) = (1 + √3 r / l) · exp(−√3 r / l)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers documented as "device" are HIP device memory owned by the
+ *    caller; the library never frees or keeps them after the call returns.
+ *    Pointers documented as "host" are ordinary host memory.
+ *  - Matrices are row-major: X is n×d, and every block of vectors (V, Y, B,
+ *    Xsol, Z) is n×k with element (i, c) at offset i·k + c.
+ *  - Element type: double for HIGP_FP64; float for HIGP_FP32 and HIGP_BF16
+ *    (in the BF16 form only the kernel tile and V are rounded to bfloat16,
+ *    inside the kernel, and products are accumulated in FP32).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is ordered
+ *    on that stream.  higp_kmatvec and higp_kmatvec_grad only enqueue work and
+ *    return; higp_pcg and higp_slq_logdet synchronise the stream before they
+ *    fill their host outputs.
+ *  - Calls are stateless and reentrant (the paper's Python interfaces are
+ *    stateless, "Design and Implementation"); any scratch memory is
+ *    allocated stream-ordered and released before the call returns.
+ *  - Return value: HIGP_OK (0) on success, a negative HIGP_ERR_* code
+ *    otherwise; higp_last_error() then returns a message for the calling
+ *    thread.  Invalid arguments are detected before any work is enqueued.
+ */
+#ifndef HIGP_H
+#define HIGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HIGP_OK 0
+#define HIGP_ERR_INVALID_ARG (-1) /* a size, pointer or parameter is out of range */
+#define HIGP_ERR_UNSUPPORTED (-2) /* a valid combination this build does not implement */
+#define HIGP_ERR_OOM (-3)         /* device scratch allocation failed */
+#define HIGP_ERR_HIP (-4)         /* a HIP runtime call failed (message has the detail) */
+
+#define HIGP_MAX_D 8  /* largest point dimension d */
+#define HIGP_MAX_K 64 /* largest number of vectors k per call */
+
+typedef enum { HIGP_GAUSSIAN = 0, HIGP_MATERN32 = 1 } higp_kernel;
+
+typedef enum {
+  HIGP_FP64 = 0, /* everything in double */
+  HIGP_FP32 = 1, /* distances, kernel values and the K-tile×V product in float */
+  HIGP_BF16 = 2  /* kernel tile and V rounded to bfloat16, FP32 accumulation */
+} higp_precision;
+
+/* One GP problem: K̂ = f²·k(X, X; l) + s·I.
+ * X: device, n×d row-major (double for HIGP_FP64, float otherwise).
+ * Valid: n ≥ 1, 1 ≤ d ≤ HIGP_MAX_D, l > 0, s ≥ 0, f finite.               */
+typedef struct {
+  int32_t kernel; /* higp_kernel */
+  int32_t prec;   /* higp_precision */
+  int64_t n;
+  int32_t d;
+  int32_t reserved; /* must be 0 */
+  const void* X;
+  double l, f, s;
+} higp_problem;
+
+/* Y = K̂·V — the on-the-fly kernel MatVec ("Statement of Need": small kernel
+ * matrix blocks are formed, used in the MatVec and discarded).
+ * V: device n×k, Y: device n×k (must not overlap V); 1 ≤ k ≤ HIGP_MAX_K.
+ * K̂ is never stored.  Asynchronous on `stream`.                            */
+int higp_kmatvec(const higp_problem* p, int32_t k, const void* V, void* Y,
+                 void* stream);
+
+/* Derivative MatVecs ∂K̂/∂θ·V for θ ∈ {l, f, s} (the quantities inside the
+ * gradient of the negative log marginal likelihood, "Gaussian Processes"),
+ * with ∂K̂/∂l = f²·∂k/∂l, ∂K̂/∂f = 2f·k(X, X; l), ∂K̂/∂s = I.
+ * Each output is device n×k and may be NULL (not computed); KV receives
+ * K̂·V from the same kernel tiles.  At least one output must be non-NULL and
+ * none may overlap V.  Asynchronous on `stream`.                           */
+int higp_kmatvec_grad(const higp_problem* p, int32_t k, const void* V,
+                      void* KV, void* dL_V, void* dF_V, void* dS_V,
+                      void* stream);
+
+/* Options of higp_pcg.                                                     */
+typedef struct {
+  double tol;           /* stop column c when ‖r_c‖₂ ≤ tol·‖b_c‖₂ (recursive r); > 0 */
+  int32_t max_iter;     /* cap on iterations per column; ≥ 1 */
+  int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂) */
+  int32_t refine_every; /* R > 0: replace r by b − K̂x (FP32-or-better MatVec)
+                           after every R-th iteration; 0 = off */
+  int32_t use_x0;       /* 1: Xsol holds the initial guess on entry; 0: x0 = 0 */
+  int32_t check_every;  /* host convergence poll period (≥ 1; 0 = library default).
+                           Converged columns are frozen on the device, so this
+                           changes only when the call returns, never the result. */
+  int32_t reserved;     /* must be 0 */
+} higp_pcg_opts;
+
+/* Per-column results of higp_pcg (host arrays of length k, caller-owned). */
+typedef struct {
+  int32_t* iters;     /* iterations taken */
+  double* relres;     /* final recursive relative residual ‖r‖/‖b‖ */
+  int32_t* converged; /* 1 if relres ≤ tol, else 0 */
+} higp_pcg_info;
+
+/* Solve K̂·Xsol = B by preconditioned CG (the paper approximates K̂⁻¹y with
+ * PCG, Saad 2003, "Gaussian Processes"), for k right-hand sides at once:
+ * k independent CG recurrences sharing one k-column MatVec per iteration.
+ * CG scalars are FP64; the iterate x and residual r are kept in FP64 on the
+ * device; the search direction enters the MatVec in the problem's precision.
+ * B: device n×k; Xsol: device n×k (initial guess on entry if use_x0).
+ * Not converging within max_iter is not an error (converged[c] = 0).
+ * Synchronises `stream` before returning.                                  */
+int higp_pcg(const higp_problem* p, int32_t k, const void* B, void* Xsol,
+             const higp_pcg_opts* opts, higp_pcg_info* info, void* stream);
+
+/* log|K̂| by eq. (1) with M = I (precond 0) or M = diag(K̂) (precond 1), its
+ * second term estimated by stochastic Lanczos quadrature (Ubaru et al. 2017,
+ * cited in "Gaussian Processes"): for each probe z, nsteps Lanczos steps on
+ * M^{-1/2}K̂M^{-1/2} from z/‖z‖ (full reorthogonalisation when reorth = 1),
+ * T = SΘSᵀ in FP64 on the host, and ‖z‖²·Σ_k S_{1k}²·log θ_k.
+ * A probe stops early (shorter T) when β_j ≤ 1e-12·max_{i≤j}|α_i|.
+ * Z: device n×nprobe probe block in the problem's precision (normally ±1).
+ *    Z = NULL is not supported by this build (HIGP_ERR_UNSUPPORTED); pass
+ *    the probes explicitly.  `seed` is reserved and ignored.
+ * logdet: host, receives log|M| + mean of the probes' quadratures.
+ * per_probe: host array of nprobe (may be NULL): log|M| + each probe's value.
+ * 1 ≤ nprobe ≤ HIGP_MAX_K, 1 ≤ nsteps ≤ 1024.  Synchronises `stream`.      */
+int higp_slq_logdet(const higp_problem* p, int32_t nprobe, int32_t nsteps,
+                    const void* Z, uint64_t seed, int32_t reorth,
+                    int32_t precond, double* logdet, double* per_probe,
+                    void* stream);
+
+/* Host utility: eigenvalues θ[0..m-1] and first eigenvector components
+ * τ[0..m-1] of the symmetric tridiagonal T with diagonal a[0..m-1] and
+ * off-diagonal b[0..m-2] — the FP64 eigen-solve inside higp_slq_logdet
+ * (implicit symmetric QR with Wilkinson shifts).  All pointers are host
+ * memory; b may be NULL when m = 1.  The eigenvalues are not sorted.
+ * Returns HIGP_ERR_INVALID_ARG for m < 1 or a NULL pointer and
+ * HIGP_ERR_UNSUPPORTED if the iteration fails to converge.  No GPU needed. */
+int higp_tridiag_eig(int32_t m, const double* a, const double* b, double* theta,
+                     double* tau);
+
+/* Static description of an error code (never NULL).                        */
+const char* higp_error_string(int code);
+
+/* Message of the last failing call on the calling thread ("" if none).      */
+const char* higp_last_error(void);
+
+/* ABI version: major·10000 + minor·100 + patch.                            */
+int higp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIGP_H */

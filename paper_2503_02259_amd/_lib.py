@@ -1,0 +1,90 @@
+"""ctypes view of the C ABI in ``include/higp.h`` (argument marshalling only).
+
+The shared library is the in-tree ``libhigp.so`` built by
+``paper_2503_02259_amd.build``.  There is no fallback: if the library is
+missing or cannot be loaded, every call raises.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhigp.so")
+
+HIGP_OK = 0
+HIGP_ERR_INVALID_ARG = -1
+HIGP_ERR_UNSUPPORTED = -2
+HIGP_ERR_OOM = -3
+HIGP_ERR_HIP = -4
+
+GAUSSIAN = 0
+MATERN32 = 1
+FP64 = 0
+FP32 = 1
+BF16 = 2
+
+# Every symbol declared in include/higp.h.
+EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
+           "higp_tridiag_eig", "higp_error_string", "higp_last_error", "higp_version")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("prec", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("reserved", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("l", ctypes.c_double), ("f", ctypes.c_double), ("s", ctypes.c_double)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)),
+                ("relres", ctypes.POINTER(ctypes.c_double)),
+                ("converged", ctypes.POINTER(ctypes.c_int32))]
+
+
+class HigpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("higp error %d (%s): %s" % (code, _ERRNAMES.get(code, "?"), msg))
+        self.code = code
+
+
+_ERRNAMES = {HIGP_ERR_INVALID_ARG: "invalid argument", HIGP_ERR_UNSUPPORTED: "unsupported",
+             HIGP_ERR_OOM: "out of memory", HIGP_ERR_HIP: "HIP error"}
+
+_lib = None
+
+
+def lib():
+    """Load libhigp.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhigp.so not found at %s; build it with "
+                              "`python -m paper_2503_02259_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        PP = ctypes.POINTER(Problem)
+        L.higp_kmatvec.argtypes = [PP, i32, vp, vp, vp]
+        L.higp_kmatvec_grad.argtypes = [PP, i32, vp, vp, vp, vp, vp, vp]
+        L.higp_pcg.argtypes = [PP, i32, vp, vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), vp]
+        L.higp_slq_logdet.argtypes = [PP, i32, i32, vp, ctypes.c_uint64, i32, i32, dp, dp, vp]
+        L.higp_tridiag_eig.argtypes = [i32, dp, dp, dp, dp]
+        L.higp_error_string.argtypes = [ctypes.c_int]
+        L.higp_error_string.restype = ctypes.c_char_p
+        L.higp_last_error.argtypes = []
+        L.higp_last_error.restype = ctypes.c_char_p
+        L.higp_version.argtypes = []
+        for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
+                     "higp_tridiag_eig", "higp_version"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != HIGP_OK:
+        raise HigpError(code, lib().higp_last_error().decode(errors="replace"))
+    return code

@@ -1,0 +1,164 @@
+"""Python API over the C ABI: torch device tensors in, torch tensors out.
+
+Every function only marshals arguments (shapes, dtypes, device pointers and
+the current HIP stream) and calls the library; all arithmetic of the path
+runs in the HIP kernels.  Tensors must be contiguous and on a ROCm device;
+float64 selects the FP64 form, float32 the FP32 form (or the BF16 form with
+``precision="bf16"``).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, HigpError  # noqa: F401
+
+_KERNELS = {"gaussian": GAUSSIAN, "rbf": GAUSSIAN, "matern32": MATERN32, GAUSSIAN: GAUSSIAN,
+            MATERN32: MATERN32}
+
+
+def _kernel_id(kernel):
+    try:
+        return _KERNELS[kernel.lower() if isinstance(kernel, str) else kernel]
+    except KeyError:
+        raise ValueError("unknown kernel %r" % (kernel,))
+
+
+def _prec(X, precision):
+    if precision is None:
+        if X.dtype == torch.float64:
+            return FP64
+        if X.dtype == torch.float32:
+            return FP32
+        raise TypeError("X must be float64 or float32")
+    p = {"fp64": FP64, "fp32": FP32, "bf16": BF16}.get(precision, precision)
+    want = torch.float64 if p == FP64 else torch.float32
+    if X.dtype != want:
+        raise TypeError("precision %r needs %s tensors" % (precision, want))
+    return p
+
+
+def _dev(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def problem(X, kernel, l, f, s, precision=None):
+    """The ABI problem struct for points X (n×d device tensor)."""
+    if X.dim() != 2:
+        raise ValueError("X must be n×d")
+    p = _lib.Problem()
+    p.kernel = _kernel_id(kernel)
+    p.prec = _prec(X, precision)
+    p.n, p.d = X.shape
+    p.reserved = 0
+    p.X = _dev(X, "X", X.dtype)
+    p.l, p.f, p.s = float(l), float(f), float(s)
+    return p
+
+
+def _as2d(V):
+    return (V.unsqueeze(1), True) if V.dim() == 1 else (V, False)
+
+
+def kmatvec(X, V, kernel, l, f, s, precision=None, out=None, stream=None):
+    """Y = K̂·V with K̂ = f²·k(X, X; l) + s·I (on-the-fly; K̂ is never stored)."""
+    p = problem(X, kernel, l, f, s, precision)
+    V2, squeeze = _as2d(V)
+    n, k = V2.shape
+    vp = _dev(V2, "V", X.dtype, (p.n, k))
+    Y = torch.empty_like(V2) if out is None else out.view(n, k)
+    yp = _dev(Y, "out", X.dtype, (p.n, k))
+    _lib.check(_lib.lib().higp_kmatvec(ctypes.byref(p), k, vp, yp, _stream(stream, X.device)))
+    return Y[:, 0] if squeeze else Y
+
+
+def kmatvec_grad(X, V, kernel, l, f, s, precision=None, want=("kv", "dl", "df", "ds"),
+                 stream=None):
+    """(K̂V, ∂K̂/∂l·V, ∂K̂/∂f·V, ∂K̂/∂s·V); entries not in `want` are None."""
+    p = problem(X, kernel, l, f, s, precision)
+    V2, squeeze = _as2d(V)
+    n, k = V2.shape
+    vp = _dev(V2, "V", X.dtype, (p.n, k))
+    outs = [torch.empty_like(V2) if w in want else None for w in ("kv", "dl", "df", "ds")]
+    ptrs = [ctypes.c_void_p(o.data_ptr()) if o is not None else None for o in outs]
+    _lib.check(_lib.lib().higp_kmatvec_grad(ctypes.byref(p), k, vp, *ptrs,
+                                           _stream(stream, X.device)))
+    if squeeze:
+        outs = [o[:, 0] if o is not None else None for o in outs]
+    return tuple(outs)
+
+
+def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine_every=0,
+        x0=None, check_every=0, precision=None, stream=None):
+    """Solve K̂·x = b for each column of B.  Returns (x, info) with info a dict
+    of per-column numpy arrays: iters, relres (recursive), converged."""
+    p = problem(X, kernel, l, f, s, precision)
+    B2, squeeze = _as2d(B)
+    n, k = B2.shape
+    bp = _dev(B2, "B", X.dtype, (p.n, k))
+    if x0 is not None:
+        Xs = (x0.unsqueeze(1) if x0.dim() == 1 else x0).clone()
+    else:
+        Xs = torch.empty_like(B2)
+    xp = _dev(Xs, "x0", X.dtype, (p.n, k))
+    o = _lib.PcgOpts(tol=float(tol), max_iter=int(max_iter),
+                     precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
+                     refine_every=int(refine_every), use_x0=1 if x0 is not None else 0,
+                     check_every=int(check_every), reserved=0)
+    iters = np.zeros(k, dtype=np.int32)
+    relres = np.zeros(k, dtype=np.float64)
+    conv = np.zeros(k, dtype=np.int32)
+    info = _lib.PcgInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    _lib.check(_lib.lib().higp_pcg(ctypes.byref(p), k, bp, xp, ctypes.byref(o), ctypes.byref(info),
+                                  _stream(stream, X.device)))
+    res = dict(iters=iters, relres=relres, converged=conv.astype(bool))
+    if squeeze:
+        return Xs[:, 0], {key: v[0] for key, v in res.items()}
+    return Xs, res
+
+
+def slq_logdet(X, Z, kernel, l, f, s, nsteps, reorth=True, precond="jacobi", precision=None,
+               stream=None):
+    """log|K̂| by eq. (1) and stochastic Lanczos quadrature over the probe
+    columns of Z.  Returns (logdet, per_probe numpy array)."""
+    p = problem(X, kernel, l, f, s, precision)
+    n, N = Z.shape
+    zp = _dev(Z, "Z", X.dtype, (p.n, N))
+    logdet = ctypes.c_double(0.0)
+    per = np.zeros(N, dtype=np.float64)
+    _lib.check(_lib.lib().higp_slq_logdet(
+        ctypes.byref(p), N, int(nsteps), zp, 0, 1 if reorth else 0,
+        {"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond], ctypes.byref(logdet),
+        per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream, X.device)))
+    return logdet.value, per
+
+
+def tridiag_eig(a, b):
+    """Host FP64 eigen-solve used by SLQ: (θ, τ) of the tridiagonal (a, b)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    m = a.size
+    th = np.zeros(m)
+    tau = np.zeros(m)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.check(_lib.lib().higp_tridiag_eig(m, a.ctypes.data_as(dp),
+                                          b.ctypes.data_as(dp) if b.size else None,
+                                          th.ctypes.data_as(dp), tau.ctypes.data_as(dp)))
+    return th, tau

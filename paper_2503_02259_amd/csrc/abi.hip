@@ -1,0 +1,201 @@
+// C ABI entry points: argument validation, error reporting, scratch memory.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+
+namespace higp {
+
+int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
+            higp_pcg_info* info, hipStream_t st);
+int run_slq(const Problem& p, int N, int m, const void* Z, int reorth, int precond,
+            double* logdet, double* per_probe, hipStream_t st);
+
+namespace {
+thread_local char g_msg[512] = "";
+bool g_pool_ready[64] = {false};
+}  // namespace
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_msg[0] = '\0'; }
+
+int validate_problem(const higp_problem* p, Problem* out) {
+  if (!p) return set_error(HIGP_ERR_INVALID_ARG, "problem is NULL");
+  if (p->kernel != HIGP_GAUSSIAN && p->kernel != HIGP_MATERN32)
+    return set_error(HIGP_ERR_INVALID_ARG, "unknown kernel %d", p->kernel);
+  if (p->prec != HIGP_FP64 && p->prec != HIGP_FP32 && p->prec != HIGP_BF16)
+    return set_error(HIGP_ERR_INVALID_ARG, "unknown precision %d", p->prec);
+  if (p->n < 1 || p->n > (int64_t(1) << 30))
+    return set_error(HIGP_ERR_INVALID_ARG, "n = %lld out of range [1, 2^30]", (long long)p->n);
+  if (p->d < 1 || p->d > HIGP_MAX_D)
+    return set_error(HIGP_ERR_INVALID_ARG, "d = %d out of range [1, %d]", p->d, HIGP_MAX_D);
+  if (p->reserved != 0) return set_error(HIGP_ERR_INVALID_ARG, "reserved field must be 0");
+  if (!p->X) return set_error(HIGP_ERR_INVALID_ARG, "X is NULL");
+  if (!(p->l > 0.0) || !std::isfinite(p->l))
+    return set_error(HIGP_ERR_INVALID_ARG, "l must be finite and > 0");
+  if (!(p->s >= 0.0) || !std::isfinite(p->s))
+    return set_error(HIGP_ERR_INVALID_ARG, "s must be finite and >= 0");
+  if (!std::isfinite(p->f)) return set_error(HIGP_ERR_INVALID_ARG, "f must be finite");
+  out->kernel = p->kernel;
+  out->prec = p->prec;
+  out->n = p->n;
+  out->d = p->d;
+  out->X = p->X;
+  out->l = p->l;
+  out->f = p->f;
+  out->s = p->s;
+  return HIGP_OK;
+}
+
+int scratch_alloc(void** ptr, size_t bytes, hipStream_t st) {
+  int dev = 0;
+  HIGP_HIP_TRY(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
+    // Keep freed stream-ordered memory in the pool between calls instead of
+    // returning it to the driver at every synchronisation.
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready[dev] = true;
+  }
+  hipError_t e = hipMallocAsync(ptr, bytes ? bytes : 256, st);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(e == hipErrorOutOfMemory ? HIGP_ERR_OOM : HIGP_ERR_HIP,
+                     "scratch allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  return HIGP_OK;
+}
+
+void scratch_free(void* ptr, hipStream_t st) {
+  if (ptr) (void)hipFreeAsync(ptr, st);
+}
+
+namespace {
+
+size_t elem_size(int prec) { return prec == HIGP_FP64 ? 8 : 4; }
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  if (!a || !b) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+}  // namespace
+}  // namespace higp
+
+using namespace higp;
+
+extern "C" {
+
+int higp_version(void) { return 100; }
+
+const char* higp_error_string(int code) {
+  switch (code) {
+    case HIGP_OK: return "ok";
+    case HIGP_ERR_INVALID_ARG: return "invalid argument";
+    case HIGP_ERR_UNSUPPORTED: return "unsupported";
+    case HIGP_ERR_OOM: return "out of device memory";
+    case HIGP_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error code";
+  }
+}
+
+const char* higp_last_error(void) { return g_msg; }
+
+int higp_kmatvec(const higp_problem* hp, int32_t k, const void* V, void* Y, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (k < 1 || k > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
+  if (!V || !Y) return set_error(HIGP_ERR_INVALID_ARG, "V and Y must be non-NULL");
+  const size_t bytes = (size_t)p.n * k * elem_size(p.prec);
+  if (overlaps(V, Y, bytes)) return set_error(HIGP_ERR_INVALID_ARG, "Y overlaps V");
+  MatvecOut o;
+  o.kv = Y;
+  return launch_kmatvec(p, k, V, o, static_cast<hipStream_t>(stream));
+}
+
+int higp_kmatvec_grad(const higp_problem* hp, int32_t k, const void* V, void* KV, void* dL,
+                      void* dF, void* dS, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (k < 1 || k > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
+  if (!V) return set_error(HIGP_ERR_INVALID_ARG, "V must be non-NULL");
+  if (!KV && !dL && !dF && !dS)
+    return set_error(HIGP_ERR_INVALID_ARG, "at least one output must be non-NULL");
+  const size_t bytes = (size_t)p.n * k * elem_size(p.prec);
+  void* outs[4] = {KV, dL, dF, dS};
+  for (int i = 0; i < 4; ++i) {
+    if (overlaps(V, outs[i], bytes)) return set_error(HIGP_ERR_INVALID_ARG, "an output overlaps V");
+    for (int j = i + 1; j < 4; ++j)
+      if (overlaps(outs[i], outs[j], bytes))
+        return set_error(HIGP_ERR_INVALID_ARG, "two outputs overlap");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dS) HIGP_HIP_TRY(hipMemcpyAsync(dS, V, bytes, hipMemcpyDeviceToDevice, st));
+  if (!KV && !dL && !dF) return HIGP_OK;
+  MatvecOut o;
+  o.kv = KV;
+  o.dl = dL;
+  o.df = dF;
+  if (!dL && !dF) return launch_kmatvec(p, k, V, o, st);
+  return launch_kmatvec(p, k, V, o, st);
+}
+
+int higp_pcg(const higp_problem* hp, int32_t k, const void* B, void* X, const higp_pcg_opts* o,
+             higp_pcg_info* info, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (k < 1 || k > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
+  if (!B || !X || !o) return set_error(HIGP_ERR_INVALID_ARG, "B, X and opts must be non-NULL");
+  if (!(o->tol > 0.0)) return set_error(HIGP_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->max_iter < 1) return set_error(HIGP_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (o->precond != 0 && o->precond != 1)
+    return set_error(HIGP_ERR_INVALID_ARG, "precond must be 0 or 1");
+  if (o->refine_every < 0 || o->check_every < 0 || o->reserved != 0 ||
+      (o->use_x0 != 0 && o->use_x0 != 1))
+    return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
+  const size_t bytes = (size_t)p.n * k * elem_size(p.prec);
+  if (overlaps(B, X, bytes)) return set_error(HIGP_ERR_INVALID_ARG, "X overlaps B");
+  return run_pcg(p, k, B, X, *o, info, static_cast<hipStream_t>(stream));
+}
+
+int higp_slq_logdet(const higp_problem* hp, int32_t nprobe, int32_t nsteps, const void* Z,
+                    uint64_t seed, int32_t reorth, int32_t precond, double* logdet,
+                    double* per_probe, void* stream) {
+  (void)seed;
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (nprobe < 1 || nprobe > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "nprobe = %d out of range [1, %d]", nprobe, HIGP_MAX_K);
+  if (nsteps < 1 || nsteps > 1024)
+    return set_error(HIGP_ERR_INVALID_ARG, "nsteps = %d out of range [1, 1024]", nsteps);
+  if ((reorth != 0 && reorth != 1) || (precond != 0 && precond != 1))
+    return set_error(HIGP_ERR_INVALID_ARG, "reorth and precond must be 0 or 1");
+  if (!logdet) return set_error(HIGP_ERR_INVALID_ARG, "logdet must be non-NULL");
+  if (!Z) return set_error(HIGP_ERR_UNSUPPORTED, "Z = NULL (device-generated probes) is not supported");
+  return run_slq(p, nprobe, nsteps, Z, reorth, precond, logdet, per_probe,
+                 static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

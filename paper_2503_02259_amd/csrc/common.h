@@ -1,0 +1,86 @@
+// Internal declarations shared by the translation units of libhigp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "higp.h"
+
+namespace higp {
+
+// ---------------------------------------------------------------------------
+// Errors: a thread-local message beside the returned code.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+#define HIGP_HIP_TRY(expr)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::higp::set_error(e_ == hipErrorOutOfMemory ? HIGP_ERR_OOM : HIGP_ERR_HIP, \
+                               "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                               __FILE__, __LINE__);                               \
+  } while (0)
+
+#define HIGP_TRY(expr)          \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != HIGP_OK) return rc_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Vector types for MFMA operands.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Validated problem description used inside the library.
+struct Problem {
+  int kernel;  // HIGP_GAUSSIAN / HIGP_MATERN32
+  int prec;    // HIGP_FP64 / HIGP_FP32 / HIGP_BF16
+  int64_t n;
+  int d;
+  const void* X;
+  double l, f, s;
+};
+
+int validate_problem(const higp_problem* p, Problem* out);
+
+// Scratch memory, stream-ordered.  Freed with scratch_free on the same stream.
+int scratch_alloc(void** ptr, size_t bytes, hipStream_t st);
+void scratch_free(void* ptr, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// MatVec launchers (kmatvec.hip).  All asynchronous on `st`.
+//
+// Outputs: out[0] = K̂V, out[1] = ∂K̂/∂l·V, out[2] = ∂K̂/∂f·V (each may be
+// null).  V/out element type follows p.prec (double for FP64, float otherwise).
+// `prec_override` >= 0 runs the MatVec in that precision instead of p.prec
+// (used for the FP32 true-residual recompute of the BF16 form).
+struct MatvecOut {
+  void* kv = nullptr;
+  void* dl = nullptr;
+  void* df = nullptr;
+};
+int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
+                   int prec_override = -1);
+
+// ---------------------------------------------------------------------------
+// Vector kernels (blas.hip).
+// Column-wise dot products of two n×k row-major blocks, accumulated in FP64
+// with a fixed reduction order (deterministic).  `ta`, `tb`: 0 = double,
+// 1 = float.  out: device double[k].  `work` must hold
+// dot_work_doubles(n, k) doubles and `counter` one zero-initialised uint32
+// (left zero on return).
+size_t dot_work_doubles(int64_t n, int k);
+int launch_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, double* out,
+                  double* work, unsigned* counter, hipStream_t st);
+
+// y = cast(x) between double (0) and float (1), optional scale: y = a·x.
+int launch_cast_scale(int64_t count, const void* x, int tx, void* y, int ty, double a,
+                      hipStream_t st);
+
+}  // namespace higp

@@ -1,0 +1,354 @@
+// Preconditioned conjugate gradients for K̂·X = B with k right-hand sides.
+//
+// HiGP approximates K̂⁻¹y with PCG and a preconditioner M ≈ K̂ ("Gaussian
+// Processes" section, citing Saad 2003).  Here the k columns are k
+// independent CG recurrences that share one k-column MatVec per iteration.
+// All CG scalars live on the device in FP64 and are updated by the kernels
+// themselves (no host round trip per iteration); x and r are FP64 vectors;
+// the search direction p is stored in the problem's precision because it is
+// the MatVec input.  A column stops when its recursively updated residual
+// satisfies ‖r‖₂ ≤ tol·‖b‖₂ (checked after every iteration) or when it has
+// taken max_iter iterations; it is then frozen.  The host only polls the
+// number of active columns every `check_every` iterations, which decides
+// when the call returns but never changes a result.
+//
+// Jacobi preconditioning uses M = diag(K̂).  For the stationary kernels
+// supported here diag(K̂) = f²·k(0) + s = f² + s for every row, so M⁻¹ is the
+// scalar 1/(f² + s).
+//
+// Residual replacement (refine_every = R): after every R-th iteration the
+// recursive residual is replaced by b − K̂x, with x rounded to the MatVec
+// precision (FP32 for the BF16 form) and the MatVec run in FP32 or better.
+#include <vector>
+
+#include "reduce.h"
+
+namespace higp {
+namespace {
+
+struct PcgState {
+  double* x;       // n×k FP64
+  double* r;       // n×k FP64
+  double* rho;     // k
+  double* pq;      // k
+  double* beta;    // k
+  double* bnorm;   // k
+  double* relres;  // k
+  int* active;     // k
+  int* iters;      // k
+  int* nactive;    // 1
+  double* work;    // reduction partials
+  unsigned* counter;
+};
+
+struct PcgScalars {
+  double tol;
+  double minv;
+  int max_iter;
+};
+
+// Finalisation shared by the update and replacement kernels: from ‖r_c‖²
+// compute relres, count the iteration, freeze converged or capped columns,
+// and form ρ' = rᵀM⁻¹r and β = ρ'/ρ.
+__device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScalars& P, int c,
+                                               double rr, bool count_iter) {
+  if (!S.active[c]) {
+    S.beta[c] = 0.0;
+    return;
+  }
+  const int it = S.iters[c] + (count_iter ? 1 : 0);
+  S.iters[c] = it;
+  const double rel = S.bnorm[c] > 0.0 ? sqrt(rr) / S.bnorm[c] : 0.0;
+  S.relres[c] = rel;
+  const double rho_new = P.minv * rr;
+  S.beta[c] = rho_new / S.rho[c];
+  S.rho[c] = rho_new;
+  if (rel <= P.tol || it >= P.max_iter) S.active[c] = 0;
+}
+
+__device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
+  if (threadIdx.x == 0) {
+    int na = 0;
+    for (int c = 0; c < k; ++c) na += S.active[c];
+    *S.nactive = na;
+  }
+}
+
+// x += αp, r −= αq for active columns (α = ρ/pᵀq), then ‖r‖² and finish.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int64_t chunk,
+                                                          const T* __restrict__ p,
+                                                          const T* __restrict__ q, PcgState S,
+                                                          PcgScalars P, int finish) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k && S.active[c]) {
+    const double alpha = S.rho[c] / S.pq[c];
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      S.x[o] += alpha * (double)p[o];
+      const double rn = S.r[o] - alpha * (double)q[o];
+      S.r[o] = rn;
+      acc += rn * rn;
+    }
+  }
+  if (!finish) return;
+  const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
+    pcg_finish_col(S, P, col, tot, true);
+  });
+  if (last) pcg_count_active(S, k);
+}
+
+// r = b − q (true residual) for active columns, then ‖r‖² and finish.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int64_t chunk,
+                                                           const T* __restrict__ b,
+                                                           const T* __restrict__ q, PcgState S,
+                                                           PcgScalars P) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k && S.active[c]) {
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      const double rn = (double)b[o] - (double)q[o];
+      S.r[o] = rn;
+      acc += rn * rn;
+    }
+  }
+  const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
+    pcg_finish_col(S, P, col, tot, true);
+  });
+  if (last) pcg_count_active(S, k);
+}
+
+// p = M⁻¹r + βp for active columns (p in the MatVec precision).
+template <typename T>
+__global__ void pcg_pupdate(int64_t n, int k, T* __restrict__ p, PcgState S, double minv) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % k);
+    if (S.active[c]) p[e] = (T)(minv * S.r[e] + S.beta[c] * (double)p[e]);
+  }
+}
+
+// Start: x = x0 or 0; r = b − K̂x0 or b; ‖b‖, ‖r‖; p = M⁻¹r.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_start_norms(int64_t n, int k, int64_t chunk,
+                                                               const T* __restrict__ b,
+                                                               const T* __restrict__ x0,
+                                                               const T* __restrict__ q0,
+                                                               PcgState S, double* bb_out,
+                                                               double* work2,
+                                                               unsigned* counter2) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k) {
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      const double bv = (double)b[o];
+      S.x[o] = x0 ? (double)x0[o] : 0.0;
+      S.r[o] = q0 ? bv - (double)q0[o] : bv;
+      acc += bv * bv;
+    }
+  }
+  (void)block_colsum_finish(acc, k, work2, counter2, sh,
+                            [&](int col, double tot) { bb_out[col] = tot; });
+}
+
+__global__ void pcg_start_finish(int k, PcgState S, PcgScalars P, const double* bb,
+                                 const double* rr) {
+  const int c = threadIdx.x;
+  if (c < k) {
+    const double bn = sqrt(bb[c]);
+    S.bnorm[c] = bn;
+    const double rel = bn > 0.0 ? sqrt(rr[c]) / bn : 0.0;
+    S.relres[c] = rel;
+    S.rho[c] = P.minv * rr[c];
+    S.iters[c] = 0;
+    S.beta[c] = 0.0;
+    S.active[c] = (rel > P.tol && P.max_iter > 0) ? 1 : 0;
+  }
+  __syncthreads();
+  pcg_count_active(S, k);
+}
+
+template <typename T>
+__global__ void pcg_pinit(int64_t n, int k, T* __restrict__ p, const double* __restrict__ r,
+                          double minv) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = (T)(minv * r[e]);
+}
+
+unsigned elem_blocks(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+template <typename T>
+int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_opts& o,
+             higp_pcg_info* info, hipStream_t st) {
+  const int64_t n = p.n;
+  const size_t nk = (size_t)n * k;
+  const RedGrid g = red_grid(n);
+  const int wp = p.prec == HIGP_FP64 ? 0 : 1;  // MatVec element type
+  const int refine_prec = p.prec == HIGP_BF16 ? HIGP_FP32 : p.prec;
+  const T* B = static_cast<const T*>(Bv);
+  T* Xout = static_cast<T*>(Xv);
+
+  // Scratch layout.
+  const size_t nwork = (size_t)g.blocks * 64;
+  size_t bytes = 0;
+  auto take = [&](size_t b) {
+    size_t off = bytes;
+    bytes += (b + 255) / 256 * 256;
+    return off;
+  };
+  const size_t o_x = take(nk * 8), o_r = take(nk * 8), o_p = take(nk * sizeof(T)),
+               o_q = take(nk * sizeof(T)), o_q2 = take(o.refine_every > 0 ? nk * sizeof(T) : 0),
+               o_sc = take(8 * 64 * 8), o_int = take(4 * 64 * 4),
+               o_work = take(nwork * 8 * 2), o_cnt = take(2 * 4);
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, bytes, st));
+  char* base = static_cast<char*>(mem);
+  PcgState S;
+  S.x = (double*)(base + o_x);
+  S.r = (double*)(base + o_r);
+  T* P = (T*)(base + o_p);
+  T* Q = (T*)(base + o_q);
+  T* Q2 = (T*)(base + o_q2);
+  double* sc = (double*)(base + o_sc);
+  S.rho = sc;
+  S.pq = sc + 64;
+  S.beta = sc + 128;
+  S.bnorm = sc + 192;
+  S.relres = sc + 256;
+  double* bb = sc + 320;
+  double* rr0 = sc + 384;
+  int* in = (int*)(base + o_int);
+  S.active = in;
+  S.iters = in + 64;
+  S.nactive = in + 128;
+  S.work = (double*)(base + o_work);
+  double* work2 = S.work + nwork;
+  S.counter = (unsigned*)(base + o_cnt);
+  unsigned* counter2 = S.counter + 1;
+
+  PcgScalars ps;
+  ps.tol = o.tol;
+  ps.max_iter = o.max_iter;
+  ps.minv = o.precond == 1 ? 1.0 / (p.f * p.f + p.s) : 1.0;
+
+  int rc = HIGP_OK;
+  auto fail = [&](int code) {
+    scratch_free(mem, st);
+    return code;
+  };
+  if (hipMemsetAsync(S.counter, 0, 8, st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "hipMemsetAsync failed"));
+
+  // r0 = b − K̂x0 needs a MatVec of x0 when a warm start is given.
+  const T* q0 = nullptr;
+  if (o.use_x0) {
+    MatvecOut mo;
+    mo.kv = Q;
+    rc = launch_kmatvec(p, k, Xout, mo, st, refine_prec);
+    if (rc) return fail(rc);
+    q0 = Q;
+  }
+  hipLaunchKernelGGL((pcg_start_norms<T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k,
+                     g.chunk, B, o.use_x0 ? (const T*)Xout : (const T*)nullptr, q0, S, bb,
+                     work2, counter2);
+  if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
+  rc = launch_coldot(n, k, S.r, 0, S.r, 0, rr0, S.work, S.counter, st);
+  if (rc) return fail(rc);
+  hipLaunchKernelGGL(pcg_start_finish, dim3(1), dim3(64), 0, st, k, S, ps, bb, rr0);
+  hipLaunchKernelGGL((pcg_pinit<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S.r,
+                     ps.minv);
+  if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
+
+  int check = o.check_every > 0 ? o.check_every : (n >= 20000 ? 1 : 8);
+  int nact = 0;
+  if (hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "synchronisation failed"));
+
+  for (int it = 1; it <= o.max_iter && nact > 0; ++it) {
+    MatvecOut mo;
+    mo.kv = Q;
+    rc = launch_kmatvec(p, k, P, mo, st);
+    if (rc) return fail(rc);
+    rc = launch_coldot(n, k, P, wp, Q, wp, S.pq, S.work, S.counter, st);
+    if (rc) return fail(rc);
+    const bool replace = o.refine_every > 0 && it % o.refine_every == 0;
+    hipLaunchKernelGGL((pcg_update<T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k, g.chunk,
+                       (const T*)P, (const T*)Q, S, ps, replace ? 0 : 1);
+    if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
+    if (replace) {
+      // x rounded to the MatVec precision, K̂x in FP32 or better, r = b − K̂x.
+      rc = launch_cast_scale((int64_t)nk, S.x, 0, Q, wp, 1.0, st);
+      if (rc) return fail(rc);
+      MatvecOut m2;
+      m2.kv = Q2;
+      rc = launch_kmatvec(p, k, Q, m2, st, refine_prec);
+      if (rc) return fail(rc);
+      hipLaunchKernelGGL((pcg_replace<T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k,
+                         g.chunk, B, (const T*)Q2, S, ps);
+      if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
+    }
+    hipLaunchKernelGGL((pcg_pupdate<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S,
+                       ps.minv);
+    if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
+    if (it % check == 0 || it == o.max_iter) {
+      if (hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(set_error(HIGP_ERR_HIP, "synchronisation failed"));
+    }
+  }
+
+  // Results.
+  rc = launch_cast_scale((int64_t)nk, S.x, 0, Xout, wp, 1.0, st);
+  if (rc) return fail(rc);
+  std::vector<int> it_h(k);
+  std::vector<double> rel_h(k);
+  if (hipMemcpyAsync(it_h.data(), S.iters, k * sizeof(int), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(rel_h.data(), S.relres, k * sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "result copy failed"));
+  scratch_free(mem, st);
+  for (int c = 0; c < k; ++c) {
+    if (info && info->iters) info->iters[c] = it_h[c];
+    if (info && info->relres) info->relres[c] = rel_h[c];
+    if (info && info->converged) info->converged[c] = rel_h[c] <= o.tol ? 1 : 0;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess)
+    return set_error(HIGP_ERR_HIP, "synchronisation failed");
+  return HIGP_OK;
+}
+
+}  // namespace
+
+int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
+            higp_pcg_info* info, hipStream_t st) {
+  if (p.prec == HIGP_FP64) return pcg_impl<double>(p, k, B, X, o, info, st);
+  return pcg_impl<float>(p, k, B, X, o, info, st);
+}
+
+}  // namespace higp

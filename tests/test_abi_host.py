@@ -1,0 +1,128 @@
+"""C-ABI checks that need no GPU: the library loads and exports every symbol
+declared in include/higp.h, invalid arguments are rejected before any work is
+enqueued, and the host FP64 tridiagonal eigen-solver is right."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_2503_02259_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "higp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(higp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 8
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(_lib.EXPORTS)
+    assert L.higp_version() >= 100
+
+
+def _prob(**kw):
+    p = _lib.Problem(kernel=0, prec=1, n=10, d=3, reserved=0, X=ctypes.c_void_p(0x1000),
+                     l=0.5, f=1.0, s=0.01)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", -5), ("d", 0), ("d", 9), ("l", 0.0),
+                                         ("l", -1.0), ("s", -1e-3), ("kernel", 7), ("prec", 5),
+                                         ("reserved", 1), ("X", None), ("l", float("nan")),
+                                         ("f", float("inf"))])
+def test_kmatvec_rejects_bad_problem(field, value):
+    L = _lib.lib()
+    p = _prob(**{field: value})
+    rc = L.higp_kmatvec(ctypes.byref(p), 4, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000), None)
+    assert rc == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_last_error().decode()
+
+
+@pytest.mark.parametrize("k", [0, 65, -1])
+def test_kmatvec_rejects_bad_k(k):
+    L = _lib.lib()
+    p = _prob()
+    rc = L.higp_kmatvec(ctypes.byref(p), k, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000), None)
+    assert rc == _lib.HIGP_ERR_INVALID_ARG
+
+
+def test_rejects_null_and_overlapping_buffers():
+    L = _lib.lib()
+    p = _prob()
+    assert L.higp_kmatvec(ctypes.byref(p), 4, None, ctypes.c_void_p(0x9000), None) == _lib.HIGP_ERR_INVALID_ARG
+    # Y starts inside V (n·k·4 = 160 bytes)
+    assert L.higp_kmatvec(ctypes.byref(p), 4, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000 + 64),
+                          None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_kmatvec_grad(ctypes.byref(p), 4, ctypes.c_void_p(0x2000), None, None, None, None,
+                               None) == _lib.HIGP_ERR_INVALID_ARG
+
+
+def test_pcg_and_slq_reject_bad_options():
+    L = _lib.lib()
+    p = _prob()
+    info = _lib.PcgInfo()
+    for kw in (dict(tol=0.0), dict(max_iter=0), dict(precond=2), dict(refine_every=-1),
+               dict(use_x0=3), dict(reserved=1)):
+        o = _lib.PcgOpts(tol=1e-6, max_iter=10, precond=1, refine_every=0, use_x0=0,
+                         check_every=0, reserved=0)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        rc = L.higp_pcg(ctypes.byref(p), 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000),
+                        ctypes.byref(o), ctypes.byref(info), None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG, kw
+    ld = ctypes.c_double()
+    for N, m, reo in ((0, 10, 1), (65, 10, 1), (4, 0, 1), (4, 2000, 1), (4, 10, 2)):
+        rc = L.higp_slq_logdet(ctypes.byref(p), N, m, ctypes.c_void_p(0x2000), 0, reo, 1,
+                               ctypes.byref(ld), None, None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG
+    rc = L.higp_slq_logdet(ctypes.byref(p), 4, 10, None, 0, 1, 1, ctypes.byref(ld), None, None)
+    assert rc == _lib.HIGP_ERR_UNSUPPORTED
+
+
+def test_error_strings():
+    L = _lib.lib()
+    for code in (0, -1, -2, -3, -4, -99):
+        assert L.higp_error_string(code)
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (2, 1), (7, 2), (30, 3), (50, 4), (200, 5)])
+def test_tridiag_eig_matches_lapack(m, seed):
+    from paper_2503_02259_amd.api import tridiag_eig
+    g = np.random.default_rng(seed)
+    a = g.standard_normal(m) * 3 + 1
+    b = g.random(m - 1) + 0.01
+    th, tau = tridiag_eig(a, b)
+    if m == 1:
+        assert th[0] == a[0] and tau[0] == 1.0
+        return
+    lam, S = scipy.linalg.eigh_tridiagonal(a, b)
+    i = np.argsort(th)
+    np.testing.assert_allclose(th[i], lam, rtol=1e-12, atol=1e-12 * np.abs(lam).max())
+    np.testing.assert_allclose(np.abs(tau[i]), np.abs(S[0]), atol=1e-10)
+    # Σ τ² log θ (the quadrature) for a positive definite shift
+    a2 = a + 2 * np.abs(lam).max()
+    th2, tau2 = tridiag_eig(a2, b)
+    l2, S2 = scipy.linalg.eigh_tridiagonal(a2, b)
+    assert abs(np.sum(tau2 ** 2 * np.log(th2)) - np.sum(S2[0] ** 2 * np.log(l2))) < 1e-12 * m
+
+
+def test_tridiag_eig_clustered_and_split():
+    from paper_2503_02259_amd.api import tridiag_eig
+    a = np.array([1.0, 1.0, 1.0, 5.0, 5.0, 1e-8])
+    b = np.array([1e-20, 0.0, 1e-9, 1e-30, 0.5])
+    th, tau = tridiag_eig(a, b)
+    lam, S = scipy.linalg.eigh_tridiagonal(a, b)
+    np.testing.assert_allclose(np.sort(th), lam, rtol=1e-12, atol=1e-15)
+    assert abs(np.sum(tau ** 2) - 1.0) < 1e-14
