@@ -97,13 +97,22 @@ typedef struct {
   double tol;           /* stop column c when ‖r_c‖₂ ≤ tol·‖b_c‖₂ (recursive r); > 0 */
   int32_t max_iter;     /* cap on iterations per column; ≥ 1 */
   int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂) */
-  int32_t refine_every; /* R > 0: replace r by b − K̂x (FP32-or-better MatVec)
-                           after every R-th iteration; 0 = off */
+  int32_t refine_every; /* R > 0: after every R-th iteration replace the recursive
+                           residual by b − K̂x computed with the iterate x (FP64)
+                           and a MatVec in precision refine_prec; 0 = off */
   int32_t use_x0;       /* 1: Xsol holds the initial guess on entry; 0: x0 = 0 */
   int32_t check_every;  /* host convergence poll period (≥ 1; 0 = library default).
                            Converged columns are frozen on the device, so this
                            changes only when the call returns, never the result. */
-  int32_t reserved;     /* must be 0 */
+  int32_t refine_prec;  /* precision of the replacement MatVec: HIGP_FP64 (x and
+                           the points widened to double; the residual is then
+                           accurate to FP64, so the tolerance holds for the true
+                           residual) or HIGP_FP32 (x rounded to float: cheaper,
+                           accurate only to the FP32 floor u·‖|K̂||x|‖/‖b‖) */
+  void* x_fp64;         /* optional (NULL = unused): device n×k double buffer that
+                           receives the FP64 iterate, which is more accurate than
+                           Xsol when the problem is FP32/BF16; must not overlap B
+                           or Xsol */
 } higp_pcg_opts;
 
 /* Per-column results of higp_pcg (host arrays of length k, caller-owned). */

@@ -36,7 +36,7 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("refine_prec", ctypes.c_int32), ("x_fp64", ctypes.c_void_p)]
 
 
 class PcgInfo(ctypes.Structure):

@@ -104,9 +104,13 @@ def kmatvec_grad(X, V, kernel, l, f, s, precision=None, want=("kv", "dl", "df", 
 
 
 def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine_every=0,
-        x0=None, check_every=0, precision=None, stream=None):
+        x0=None, check_every=0, precision=None, refine_prec="fp64", return_fp64=False,
+        stream=None):
     """Solve K̂·x = b for each column of B.  Returns (x, info) with info a dict
-    of per-column numpy arrays: iters, relres (recursive), converged."""
+    of per-column numpy arrays: iters, relres (tracked residual), converged.
+    With refine_every = R > 0 the tracked residual is replaced by b − K̂x every
+    R iterations, the MatVec then running in `refine_prec` ("fp64"/"fp32").
+    With return_fp64 the FP64 iterate is returned as well: (x, x64, info)."""
     p = problem(X, kernel, l, f, s, precision)
     B2, squeeze = _as2d(B)
     n, k = B2.shape
@@ -119,7 +123,12 @@ def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine
     o = _lib.PcgOpts(tol=float(tol), max_iter=int(max_iter),
                      precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
                      refine_every=int(refine_every), use_x0=1 if x0 is not None else 0,
-                     check_every=int(check_every), reserved=0)
+                     check_every=int(check_every),
+                     refine_prec={"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[refine_prec])
+    x64 = None
+    if return_fp64:
+        x64 = torch.empty(B2.shape, dtype=torch.float64, device=B2.device)
+        o.x_fp64 = x64.data_ptr()
     iters = np.zeros(k, dtype=np.int32)
     relres = np.zeros(k, dtype=np.float64)
     conv = np.zeros(k, dtype=np.int32)
@@ -130,8 +139,10 @@ def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine
                                   _stream(stream, X.device)))
     res = dict(iters=iters, relres=relres, converged=conv.astype(bool))
     if squeeze:
-        return Xs[:, 0], {key: v[0] for key, v in res.items()}
-    return Xs, res
+        res = {key: v[0] for key, v in res.items()}
+        Xs = Xs[:, 0]
+        x64 = x64[:, 0] if x64 is not None else None
+    return (Xs, x64, res) if return_fp64 else (Xs, res)
 
 
 def slq_logdet(X, Z, kernel, l, f, s, nsteps, reorth=True, precond="jacobi", precision=None,

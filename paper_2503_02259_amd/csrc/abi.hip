@@ -101,7 +101,7 @@ using namespace higp;
 
 extern "C" {
 
-int higp_version(void) { return 100; }
+int higp_version(void) { return 200; }
 
 const char* higp_error_string(int code) {
   switch (code) {
@@ -171,11 +171,15 @@ int higp_pcg(const higp_problem* hp, int32_t k, const void* B, void* X, const hi
   if (o->max_iter < 1) return set_error(HIGP_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (o->precond != 0 && o->precond != 1)
     return set_error(HIGP_ERR_INVALID_ARG, "precond must be 0 or 1");
-  if (o->refine_every < 0 || o->check_every < 0 || o->reserved != 0 ||
-      (o->use_x0 != 0 && o->use_x0 != 1))
+  if (o->refine_every < 0 || o->check_every < 0 || (o->use_x0 != 0 && o->use_x0 != 1))
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
+  if (o->refine_prec != HIGP_FP64 && o->refine_prec != HIGP_FP32)
+    return set_error(HIGP_ERR_INVALID_ARG, "refine_prec must be HIGP_FP64 or HIGP_FP32");
   const size_t bytes = (size_t)p.n * k * elem_size(p.prec);
   if (overlaps(B, X, bytes)) return set_error(HIGP_ERR_INVALID_ARG, "X overlaps B");
+  if (o->x_fp64 && (overlaps(o->x_fp64, B, (size_t)p.n * k * 8) ||
+                    overlaps(o->x_fp64, X, (size_t)p.n * k * 8)))
+    return set_error(HIGP_ERR_INVALID_ARG, "x_fp64 overlaps B or Xsol");
   return run_pcg(p, k, B, X, *o, info, static_cast<hipStream_t>(stream));
 }
 

@@ -1,0 +1,467 @@
+// FP32 on-the-fly kernel MatVec (and derivative MatVec) with
+// v_mfma_f32_32x32x2f32 on gfx950.
+//
+// HiGP forms small kernel-matrix blocks, multiplies them into the vectors
+// immediately and discards them ("Statement of Need", MatVec paragraph).
+// Here every kernel value is formed in a register, directly in the MFMA
+// A-operand slot, and multiplied by the matrix core with a V tile held in
+// LDS; K is never stored.
+//
+// Work decomposition (stream-K).  The row-major space of items (row tile I of
+// BM rows) × (J tile of 128 points) is cut into equal contiguous shares, one
+// per workgroup, with exactly as many workgroups as fit on the GPU at once.
+// A workgroup walks its share; J tiles are copied global → LDS directly
+// (buffer_load … lds, double-buffered, no staging registers); whenever the
+// row tile changes it writes its partial sums for the finished row-tile
+// segment to a private slot.  An epilogue kernel adds, for every output row,
+// the slots of the workgroups that covered its row tile, in workgroup order
+// (deterministic, no atomics), and applies f², s and the derivative factors.
+//
+// Per wave: RB blocks of 32 rows.  At MFMA step j0 lane l supplies
+// K[i0 + l%32][j0 + l/32] for each row block; the RB products share the x_j
+// and V reads.  NB blocks of 32 columns go through the matrix core; NV ≤ 2
+// trailing columns are accumulated on the VALU (k = 33 is 32 MFMA columns
+// plus one VALU column rather than padding to 64).  Accumulator layout
+// (32×32): lane l, register r holds row 8(r/4) + 4(l/32) + r%4, column l%32.
+//
+// Accumulation is FP32 within one J tile (64 MFMA steps); tile sums are added
+// into FP64 running totals, so a long FP32 accumulation over n terms does
+// not build up rounding error.
+//
+// Points come from a prepared copy Xp (step a1): x̃ padded to P = 4 or 8
+// floats with zeros, and padded to whole J tiles with far-away sentinel
+// points (all coordinates kFar) whose kernel value is exactly 0, so no tile
+// needs masking in the inner loop.  V is read as a contiguous block of 128·k
+// floats per tile (row stride k in LDS); reads past its end return 0.
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+
+#include "kvalue.h"
+
+namespace higp {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBJ = 128;       // J points per LDS tile
+constexpr float kFar = 1e18f;  // squared distance ~1e36: exp2 underflows to exactly 0
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// a1: x̃ = x·xs padded to P floats; rows n..npad−1 are far-away sentinels.
+template <int P>
+__global__ void prep_points_f32(int64_t n, int64_t npad, int d, const float* __restrict__ X,
+                                float xs, float* __restrict__ Xp) {
+  const int64_t count = npad * P;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / P;
+    const int c = (int)(e % P);
+    Xp[e] = i >= n ? kFar : (c < d ? X[i * d + c] * xs : 0.0f);
+  }
+}
+
+// dst[0..count_pad) = src[0..count) followed by zeros.
+__global__ void copy_pad_f32(int64_t count, int64_t count_pad, const float* __restrict__ src,
+                             float* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count_pad;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = e < count ? src[e] : 0.0f;
+}
+
+// Buffer resource over `bytes` bytes at `base` (reads past the end return 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const int nrec = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
+}
+
+struct Args {
+  const float* Xp;  // npad×P prepared points
+  const float* V;   // n×k (16-byte aligned, readable up to nk_pad elements)
+  float* part;      // partial slots [grid·maxseg][BM][k]: Σ k·v
+  float* part2;     // same layout: Σ k_l·v (GRAD)
+  int64_t n;
+  int64_t nk_pad;
+  int64_t items;    // row tiles × J tiles
+  int jt_count;     // J tiles
+  int k, maxseg;
+};
+
+template <int KERN, int D, int NB, int NV, int RB, bool GRAD>
+__global__ __launch_bounds__(256) void kmv_f32(Args a) {
+  constexpr int P = D <= 4 ? 4 : 8;
+  constexpr int BM = 32 * RB * kWaves;
+  constexpr int NBa = NB > 0 ? NB : 1;
+  constexpr int NVa = NV > 0 ? NV : 1;
+  constexpr int G2 = GRAD ? 2 : 1;  // contractions: k·v and (GRAD) k_l·v
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  const int k = a.k;
+  const int vtile = kBJ * k;
+  float* Xs = smem;                 // [2][kBJ][P]
+  float* Vs = smem + 2 * kBJ * P;   // [2][kBJ·k]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+
+  const int64_t grid = gridDim.x;
+  const int64_t it0 = (int64_t)blockIdx.x * a.items / grid;
+  const int64_t it1 = ((int64_t)blockIdx.x + 1) * a.items / grid;
+  if (it0 >= it1) return;
+  const int JT = a.jt_count;
+  const int64_t rt_first = it0 / JT;
+
+  float xi[RB][P];
+  auto load_rows = [&](int64_t rt) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t i = rt * BM + wave * 32 * RB + rb * 32 + l32;
+#pragma unroll
+      for (int c = 0; c < P; ++c) xi[rb][c] = i < a.n ? a.Xp[i * P + c] : 0.0f;
+    }
+  };
+
+  f32x16 acc[G2][RB][NBa];
+  double tot[G2][RB][NBa][16];
+  float accv[G2][RB][NVa];
+  double totv[G2][RB][NVa];
+#pragma unroll
+  for (int g = 0; g < G2; ++g)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[g][rb][b] = f32x16{0};
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[g][rb][b][r] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        accv[g][rb][v] = 0.0f;
+        totv[g][rb][v] = 0.0;
+      }
+    }
+
+  // Global → LDS copy of J tile `jt` into buffer `buf`: every wave issues its
+  // share of 16-byte chunks, 64 consecutive chunks (1 KB) per instruction.
+  constexpr int XC = kBJ * P / 4;  // chunks of the X tile
+  const int vchunks = vtile / 4;   // chunks of the V tile
+  auto gload = [&](int64_t jt, int buf) {
+    char* xs = reinterpret_cast<char*>(Xs + buf * kBJ * P);
+    char* vs = reinterpret_cast<char*>(Vs + buf * vtile);
+    const int64_t j0 = jt * kBJ;
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.Xp + j0 * P, (int64_t)kBJ * P * 4);
+    for (int m = wave * 64; m < XC; m += 256)
+      if (m + lane < XC)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_t*)(xs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.V + j0 * k, (a.nk_pad - j0 * k) * 4);
+    for (int m = wave * 64; m < vchunks; m += 256)
+      if (m + lane < vchunks)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, (lds_void_t*)(vs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
+  };
+
+  // Partial sums of one row-tile segment → its slot (FP64 totals, rounded once).
+  auto flush = [&](int64_t rt) {
+    const int64_t slot = (int64_t)blockIdx.x * a.maxseg + (rt - rt_first);
+    float* q1 = a.part + slot * BM * k;
+    float* q2 = GRAD ? a.part2 + slot * BM * k : nullptr;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int lrow0 = wave * 32 * RB + rb * 32;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int col = b * 32 + l32;
+        if (col < k) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int lrow = lrow0 + 8 * (r >> 2) + 4 * half + (r & 3);
+            q1[lrow * k + col] = (float)tot[0][rb][b][r];
+            if constexpr (GRAD) q2[lrow * k + col] = (float)tot[G2 - 1][rb][b][r];
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G2; ++g)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) tot[g][rb][b][r] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        // lanes l and l+32 hold the two halves of row l%32
+#pragma unroll
+        for (int g = 0; g < G2; ++g) totv[g][rb][v] += __shfl_xor(totv[g][rb][v], 32);
+        if (half == 0) {
+          q1[(lrow0 + l32) * k + NB * 32 + v] = (float)totv[0][rb][v];
+          if constexpr (GRAD) q2[(lrow0 + l32) * k + NB * 32 + v] = (float)totv[G2 - 1][rb][v];
+        }
+#pragma unroll
+        for (int g = 0; g < G2; ++g) totv[g][rb][v] = 0.0;
+      }
+    }
+  };
+
+  // Walk the share one row-tile segment at a time, tracking (row tile, J
+  // tile) incrementally.
+  int64_t rt = rt_first;
+  int jt = (int)(it0 - rt_first * JT);
+  int64_t left = it1 - it0;
+  int cur = 0;
+  gload(jt, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  while (left > 0) {
+    const int seg = left < (int64_t)(JT - jt) ? (int)left : JT - jt;
+    load_rows(rt);
+    for (int sgi = 0; sgi < seg; ++sgi) {
+    const int jn = jt + 1 == JT ? 0 : jt + 1;
+    if (left > 1) gload(jn, cur ^ 1);
+
+    const float* xs = Xs + cur * kBJ * P + half * P;
+    const float* vb_base = Vs + cur * vtile + half * k + l32;
+    const float* vv_base = Vs + cur * vtile + half * k + NB * 32;
+#pragma unroll 2
+    for (int st = 0; st < kBJ / 2; ++st) {
+      const float* xj = xs + st * 2 * P;
+      float kv[RB], kg[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        float r2 = 0.0f;
+        const f32x4 xa = *reinterpret_cast<const f32x4*>(xj);
+        if constexpr (P == 4) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const float df = xi[rb][c] - xa[c];
+            r2 = fmaf(df, df, r2);
+          }
+        } else {
+          const f32x4 xb = *reinterpret_cast<const f32x4*>(xj + 4);
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const float df = xi[rb][c] - (c < 4 ? xa[c & 3] : xb[c & 3]);
+            r2 = fmaf(df, df, r2);
+          }
+        }
+        kval_f32<KERN, GRAD>(r2, kv[rb], kg[rb]);
+      }
+      const int vo = st * 2 * k;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float vb = vb_base[vo + b * 32];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          acc[0][rb][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(kv[rb], vb, acc[0][rb][b], 0, 0, 0);
+          if constexpr (GRAD)
+            acc[G2 - 1][rb][b] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(kg[rb], vb, acc[G2 - 1][rb][b], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float vv = vv_base[vo + v];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          accv[0][rb][v] = fmaf(kv[rb], vv, accv[0][rb][v]);
+          if constexpr (GRAD) accv[G2 - 1][rb][v] = fmaf(kg[rb], vv, accv[G2 - 1][rb][v]);
+        }
+      }
+    }
+    // Tile sums → FP64 running totals.
+#pragma unroll
+    for (int g = 0; g < G2; ++g)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) tot[g][rb][b][r] += (double)acc[g][rb][b][r];
+          acc[g][rb][b] = f32x16{0};
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          totv[g][rb][v] += (double)accv[g][rb][v];
+          accv[g][rb][v] = 0.0f;
+        }
+      }
+
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    jt = jn;
+    cur ^= 1;
+    --left;
+    }
+    flush(rt);
+    ++rt;
+  }
+}
+
+// For every output element: the sum of the partial slots of the workgroups
+// that covered its row tile, in workgroup order, then K̂V = f²·Σ + s·V and
+// the derivative outputs.
+__global__ void kmv_f32_epilogue(const float* __restrict__ part, const float* __restrict__ part2,
+                                 const float* __restrict__ V, float* o1, float* o2, float* o3,
+                                 int64_t n, int k, int bm, int64_t items, int jt_count,
+                                 int64_t grid, int maxseg, double f2, double s, double cl,
+                                 double cf) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / k;
+    const int c = (int)(e % k);
+    const int64_t rt = i / bm;
+    const int lr = (int)(i % bm);
+    const int64_t lo = rt * jt_count, hi = lo + jt_count;
+    // first workgroup whose share [w·items/grid, (w+1)·items/grid) reaches lo
+    int64_t w = lo * grid / items;
+    while (w > 0 && w * items / grid > lo) --w;
+    while (w + 1 < grid && (w + 1) * items / grid <= lo) ++w;
+    double s1 = 0.0, s2 = 0.0;
+    for (; w < grid; ++w) {
+      const int64_t a0 = w * items / grid;
+      const int64_t a1 = (w + 1) * items / grid;
+      if (a0 >= hi) break;
+      if (a1 <= a0 || a1 <= lo) continue;
+      const int64_t slot = w * maxseg + (rt - a0 / jt_count);
+      const int64_t o = (slot * bm + lr) * k + c;
+      s1 += (double)part[o];
+      if (part2) s2 += (double)part2[o];
+    }
+    if (o1) o1[e] = (float)(f2 * s1 + s * (double)V[e]);
+    if (o2) o2[e] = (float)(cl * s2);
+    if (o3) o3[e] = (float)(cf * s1);
+  }
+}
+
+using Fn = void (*)(Args);
+
+template <int KERN, int D, int NB, int NV, bool GRAD>
+Fn inst(int* rb) {
+  constexpr int RB = (NB == 2 || GRAD) ? 1 : 2;
+  *rb = RB;
+  return kmv_f32<KERN, D, NB, NV, RB, GRAD>;
+}
+
+template <int KERN, int D, bool GRAD>
+Fn pick_cols(int k, int* rb) {
+  if (k == 1) return inst<KERN, D, 0, 1, GRAD>(rb);
+  if (k == 2) return inst<KERN, D, 0, 2, GRAD>(rb);
+  if (k <= 32) return inst<KERN, D, 1, 0, GRAD>(rb);
+  if (k == 33) return inst<KERN, D, 1, 1, GRAD>(rb);
+  if (k == 34) return inst<KERN, D, 1, 2, GRAD>(rb);
+  return inst<KERN, D, 2, 0, GRAD>(rb);
+}
+
+template <int KERN, bool GRAD>
+Fn pick_d(int d, int k, int* rb) {
+  if (d <= 2) return pick_cols<KERN, 2, GRAD>(k, rb);
+  if (d == 3) return pick_cols<KERN, 3, GRAD>(k, rb);
+  if (d == 4) return pick_cols<KERN, 4, GRAD>(k, rb);
+  return pick_cols<KERN, 8, GRAD>(k, rb);
+}
+
+// Resident workgroups per CU for (kernel, LDS bytes), cached per device.
+int blocks_per_cu(Fn fn, size_t lds) {
+  static std::mutex mu;
+  static std::unordered_map<uint64_t, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint64_t key = reinterpret_cast<uint64_t>(fn) ^ ((uint64_t)lds << 40) ^ ((uint64_t)dev << 60);
+  std::lock_guard<std::mutex> g(mu);
+  auto itc = cache.find(key);
+  if (itc != cache.end()) return itc->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), 256,
+                                                   lds) != hipSuccess ||
+      nb < 1)
+    nb = 1;
+  cache[key] = nb;
+  return nb;
+}
+
+}  // namespace
+
+int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, hipStream_t st,
+                       int num_cus) {
+  const bool grad = out.dl != nullptr || out.df != nullptr;
+  int rb = 1;
+  Fn fn;
+  if (p.kernel == HIGP_GAUSSIAN)
+    fn = grad ? pick_d<HIGP_GAUSSIAN, true>(p.d, k, &rb) : pick_d<HIGP_GAUSSIAN, false>(p.d, k, &rb);
+  else
+    fn = grad ? pick_d<HIGP_MATERN32, true>(p.d, k, &rb) : pick_d<HIGP_MATERN32, false>(p.d, k, &rb);
+  const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
+  const double cl = p.f * p.f * dl_factor(p.kernel, HIGP_FP32, p.l);
+
+  const int bm = 32 * rb * kWaves;
+  const int P = p.d <= 4 ? 4 : 8;
+  const int64_t nk = p.n * k;
+  const int64_t jt_count = (p.n + kBJ - 1) / kBJ;
+  const int64_t npad = jt_count * kBJ;
+  const int64_t rt_count = (p.n + bm - 1) / bm;
+  const int64_t items = rt_count * jt_count;
+  const size_t lds = (size_t)2 * kBJ * P * 4 + (size_t)2 * kBJ * k * 4;
+  if (lds > 65536 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return set_error(HIGP_ERR_HIP, "cannot reserve %zu bytes of LDS", lds);
+  const int64_t grid = std::min<int64_t>(items, (int64_t)num_cus * blocks_per_cu(fn, lds));
+  const int64_t per = (items + grid - 1) / grid;
+  const int maxseg = (int)((per + jt_count - 1) / jt_count + 1);
+
+  // Scratch: prepared points (whole J tiles); a zero-padded copy of V unless
+  // V is 16-byte aligned and n·k is a multiple of 4 (tiles move 16-byte
+  // chunks); the partial slots.
+  const bool direct_v = (reinterpret_cast<uintptr_t>(Vin) & 15) == 0 && nk % 4 == 0;
+  const int64_t nk_pad = (nk + 3) / 4 * 4;
+  const size_t xp_bytes = ((size_t)npad * P * 4 + 255) / 256 * 256;
+  const size_t v_bytes = direct_v ? 0 : ((size_t)nk_pad * 4 + 255) / 256 * 256;
+  const size_t part_bytes = ((size_t)grid * maxseg * bm * k * 4 + 255) / 256 * 256;
+  void* scratch = nullptr;
+  HIGP_TRY(scratch_alloc(&scratch, xp_bytes + v_bytes + part_bytes * (grad ? 2 : 1), st));
+  char* base = static_cast<char*>(scratch);
+  float* Xp = reinterpret_cast<float*>(base);
+  const float* V = static_cast<const float*>(Vin);
+  int rc = HIGP_OK;
+  if (!direct_v) {
+    float* Vc = reinterpret_cast<float*>(base + xp_bytes);
+    const unsigned cb = (unsigned)std::min<int64_t>((nk_pad + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_pad_f32, dim3(cb), dim3(256), 0, st, nk, nk_pad,
+                       static_cast<const float*>(Vin), Vc);
+    V = Vc;
+  }
+  {
+    const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
+    if (P == 4)
+      hipLaunchKernelGGL(prep_points_f32<4>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                         static_cast<const float*>(p.X), xs, Xp);
+    else
+      hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                         static_cast<const float*>(p.X), xs, Xp);
+  }
+  Args a{};
+  a.Xp = Xp;
+  a.V = V;
+  a.part = reinterpret_cast<float*>(base + xp_bytes + v_bytes);
+  a.part2 = grad ? reinterpret_cast<float*>(base + xp_bytes + v_bytes + part_bytes) : nullptr;
+  a.n = p.n;
+  a.nk_pad = direct_v ? nk : nk_pad;
+  a.items = items;
+  a.jt_count = (int)jt_count;
+  a.k = k;
+  a.maxseg = maxseg;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), lds, st, a);
+  const unsigned eb = (unsigned)std::min<int64_t>((nk + 255) / 256, 8LL * num_cus);
+  hipLaunchKernelGGL(kmv_f32_epilogue, dim3(eb), dim3(256), 0, st, (const float*)a.part,
+                     (const float*)a.part2, V, static_cast<float*>(out.kv),
+                     static_cast<float*>(out.dl), static_cast<float*>(out.df), p.n, k, bm, items,
+                     (int)jt_count, grid, maxseg, p.f * p.f, p.s, cl, 2.0 * p.f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) rc = set_error(HIGP_ERR_HIP, "FP32 MatVec launch failed: %s", hipGetErrorString(e));
+  scratch_free(scratch, st);
+  return rc;
+}
+
+}  // namespace higp

@@ -1,0 +1,302 @@
+// FP64 on-the-fly kernel MatVec (and derivative MatVec) with
+// v_mfma_f64_16x16x4f64 on gfx950.
+//
+// The plain-method form: distances, kernel values (software exp), products
+// and sums all in double.  Each workgroup owns a row tile I of 64 rows and a
+// chunk of the J range (split-J, so that small n still fills the GPU); J
+// tiles of X and V are staged through LDS; each lane forms one kernel value
+// per MFMA step in the A-operand slot.  Split partials are added in a fixed
+// order by an epilogue kernel (deterministic, no atomics).
+#include <algorithm>
+
+#include "kvalue.h"
+
+namespace higp {
+namespace {
+
+constexpr int kWaves = 4;
+
+template <typename T>
+struct KArgs {
+  const T* X;   // n×d row-major
+  const T* V;   // n×k row-major
+  T* o1;        // S==1: K̂V (or null); S>1: partial Σ k·v, S×n×k
+  T* o2;        // S==1: ∂K̂/∂l·V (or null); S>1: partial Σ k_l·v (GRAD only)
+  T* o3;        // S==1: ∂K̂/∂f·V (or null); unused when S>1
+  int64_t n;
+  int64_t jchunk;  // J points per split (multiple of the J tile)
+  int k, d, nsplit;
+  T xs;          // coordinate pre-scale
+  T f2, s;       // K̂ = f²K + sI (epilogue, S==1)
+  T cl, cf;      // ∂K̂/∂l = cl·Σk_l v, ∂K̂/∂f = cf·Σk v (epilogue, S==1)
+};
+
+// ---------------------------------------------------------------------------
+// FP64: v_mfma_f64_16x16x4f64.  A wave owns 16 rows; per MFMA each lane
+// supplies K[i0 + lane%16][j0 + lane/16] (4 J points per step); NB blocks of
+// 16 columns.  Output layout: lane l, register r holds row l/16 + 4r,
+// column l%16.
+
+constexpr int kBJ64 = 64;  // J points per LDS tile (FP64 kernel)
+
+template <int KERN, int D, int NB, bool GRAD>
+__global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
+  constexpr int P = D <= 4 ? 4 : 8;
+  constexpr int VC = NB * 16;
+  constexpr int BM = 16 * kWaves;
+  __shared__ double Xs[2][kBJ64][P];
+  __shared__ double Vs[2][kBJ64][VC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;        // which of the 4 J points of the step
+  const int l16 = lane & 15;
+  const int split = blockIdx.x % a.nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / a.nsplit) * BM;
+  const int64_t jbeg = (int64_t)split * a.jchunk;
+  const int64_t jend = min(a.n, jbeg + a.jchunk);
+  const int k = a.k, d = a.d;
+
+  const int64_t irow = row0 + wave * 16 + l16;
+  double xi[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    xi[c] = (irow < a.n && c < d) ? a.X[irow * d + c] * a.xs : 0.0;
+
+  f64x4 acc[NB];
+  f64x4 acc2[GRAD ? NB : 1];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    acc[b] = f64x4{0};
+    if constexpr (GRAD) acc2[b] = f64x4{0};
+  }
+
+  constexpr int XPER = (kBJ64 * D + 255) / 256;
+  constexpr int VROWS = kBJ64 / 4;
+  double xr[XPER];
+  double vr[VROWS];
+  const int vc = tid & 63;
+  const int vr0 = tid >> 6;
+
+  auto gload = [&](int64_t jt) {
+#pragma unroll
+    for (int m = 0; m < XPER; ++m) {
+      const int e = tid + 256 * m;
+      const int r = e / D, c = e % D;
+      double v = 0.0;
+      if (e < kBJ64 * D && c < d && jt + r < jend) v = a.X[(jt + r) * d + c];
+      xr[m] = v;
+    }
+#pragma unroll
+    for (int m = 0; m < VROWS; ++m) {
+      const int64_t j = jt + vr0 + 4 * m;
+      double v = 0.0;
+      if (vc < k && j < jend) v = a.V[j * k + vc];
+      vr[m] = v;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int m = 0; m < XPER; ++m) {
+      const int e = tid + 256 * m;
+      if (e < kBJ64 * D) Xs[buf][e / D][e % D] = xr[m] * a.xs;
+    }
+    if (vc < VC) {
+#pragma unroll
+      for (int m = 0; m < VROWS; ++m) Vs[buf][vr0 + 4 * m][vc] = vr[m];
+    }
+  };
+
+  if constexpr (P > D) {
+    for (int e = tid; e < 2 * kBJ64 * (P - D); e += 256) {
+      const int buf = e / (kBJ64 * (P - D));
+      const int rem = e % (kBJ64 * (P - D));
+      Xs[buf][rem / (P - D)][D + rem % (P - D)] = 0.0;
+    }
+  }
+
+  const int64_t ntiles = (jend > jbeg) ? (jend - jbeg + kBJ64 - 1) / kBJ64 : 0;
+  if (ntiles > 0) {
+    gload(jbeg);
+    lstore(0);
+  }
+  __syncthreads();
+
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int cur = (int)(t & 1);
+    const bool more = t + 1 < ntiles;
+    if (more) gload(jbeg + (t + 1) * kBJ64);
+
+#pragma unroll 2
+    for (int st = 0; st < kBJ64 / 4; ++st) {
+      const int j = 4 * st + q;
+      double r2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double df = xi[c] - Xs[cur][j][c];
+        r2 = fma(df, df, r2);
+      }
+      double kv, kg;
+      kval_f64<KERN, GRAD>(r2, kv, kg);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double vb = Vs[cur][j][b * 16 + l16];
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, vb, acc[b], 0, 0, 0);
+        if constexpr (GRAD) acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kg, vb, acc2[b], 0, 0, 0);
+      }
+    }
+
+    if (more) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  const bool direct = a.nsplit == 1;
+  double* p1 = direct ? a.o1 : a.o1 + (int64_t)split * a.n * k;
+  double* p2 = a.o2;
+  if constexpr (GRAD) {
+    if (!direct) p2 = a.o2 + (int64_t)split * a.n * k;
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int col = b * 16 + l16;
+    if (col >= k) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + wave * 16 + q + 4 * r;
+      if (row >= a.n) continue;
+      const int64_t o = row * k + col;
+      const double s1 = acc[b][r];
+      if (direct) {
+        if (a.o1) a.o1[o] = fma(a.f2, s1, a.s * a.V[o]);
+        if constexpr (GRAD) {
+          if (a.o2) a.o2[o] = a.cl * acc2[b][r];
+          if (a.o3) a.o3[o] = a.cf * s1;
+        }
+      } else {
+        p1[o] = s1;
+        if constexpr (GRAD) p2[o] = acc2[b][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue over S partials: out = f²·Σ_s P1 + s·V (and the derivative
+// outputs).  Partials are added in split order in FP64.
+
+template <typename T>
+__global__ __launch_bounds__(256) void kmv_epilogue(const T* __restrict__ P1,
+                                                    const T* __restrict__ P2,
+                                                    const T* __restrict__ V, T* o1, T* o2,
+                                                    T* o3, int64_t count, int nsplit, double f2,
+                                                    double s, double cl, double cf) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      s1 += (double)P1[sp * count + e];
+      if (P2) s2 += (double)P2[sp * count + e];
+    }
+    if (o1) o1[e] = (T)(f2 * s1 + s * (double)V[e]);
+    if (o2) o2[e] = (T)(cl * s2);
+    if (o3) o3[e] = (T)(cf * s1);
+  }
+}
+
+template <typename T>
+using KFn = void (*)(KArgs<T>);
+
+template <int KERN, int D, bool GRAD>
+KFn<double> pick_f64_cols(int k) {
+  if (k <= 16) return kmv_f64<KERN, D, 1, GRAD>;
+  if (k <= 32) return kmv_f64<KERN, D, 2, GRAD>;
+  if (k <= 48) return kmv_f64<KERN, D, 3, GRAD>;
+  return kmv_f64<KERN, D, 4, GRAD>;
+}
+
+template <int KERN, bool GRAD>
+KFn<double> pick_f64_d(int d, int k) {
+  if (d <= 2) return pick_f64_cols<KERN, 2, GRAD>(k);
+  if (d == 3) return pick_f64_cols<KERN, 3, GRAD>(k);
+  if (d == 4) return pick_f64_cols<KERN, 4, GRAD>(k);
+  return pick_f64_cols<KERN, 8, GRAD>(k);
+}
+
+// Number of J splits S (a power of two ≤ 64) so that the grid has at least
+// `want_blocks` workgroups while each split keeps `min_tiles` J tiles.
+int choose_splits(int64_t n, int bm, int bj, int min_tiles, int64_t want_blocks) {
+  const int64_t row_tiles = (n + bm - 1) / bm;
+  int s = 1;
+  while (s < 64 && row_tiles * s < want_blocks && n / (2LL * s) >= (int64_t)min_tiles * bj) s *= 2;
+  return s;
+}
+
+template <typename T>
+int launch_epilogue(const T* P1, const T* P2, const T* V, MatvecOut out, int64_t count, int S,
+                    double f2, double s, double cl, double cf, hipStream_t st, int ncus) {
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8LL * ncus);
+  hipLaunchKernelGGL(kmv_epilogue<T>, dim3((unsigned)blocks), dim3(256), 0, st, P1, P2, V,
+                     static_cast<T*>(out.kv), static_cast<T*>(out.dl), static_cast<T*>(out.df),
+                     count, S, f2, s, cl, cf);
+  return hipGetLastError() == hipSuccess ? HIGP_OK
+                                         : set_error(HIGP_ERR_HIP, "epilogue launch failed");
+}
+
+int run_f64(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
+            KFn<double> fn, double xs, double cl, int num_cus) {
+  constexpr int bm = 16 * kWaves;
+  const bool grad = out.dl != nullptr || out.df != nullptr;
+  KArgs<double> a{};
+  a.X = static_cast<const double*>(p.X);
+  a.V = static_cast<const double*>(V);
+  a.n = p.n;
+  a.k = k;
+  a.d = p.d;
+  a.xs = xs;
+  a.f2 = p.f * p.f;
+  a.s = p.s;
+  a.cl = cl;
+  a.cf = 2.0 * p.f;
+  const int S = choose_splits(p.n, bm, kBJ64, 1, 4LL * num_cus);
+  a.nsplit = S;
+  const int64_t tiles_j = (p.n + kBJ64 - 1) / kBJ64;
+  a.jchunk = ((tiles_j + S - 1) / S) * kBJ64;
+  const int64_t nblocks = ((p.n + bm - 1) / bm) * S;
+  void* scratch = nullptr;
+  if (S == 1) {
+    a.o1 = static_cast<double*>(out.kv);
+    a.o2 = static_cast<double*>(out.dl);
+    a.o3 = static_cast<double*>(out.df);
+  } else {
+    const size_t per = (size_t)p.n * k * sizeof(double) * S;
+    HIGP_TRY(scratch_alloc(&scratch, per * (grad ? 2 : 1), st));
+    a.o1 = static_cast<double*>(scratch);
+    a.o2 = grad ? reinterpret_cast<double*>(static_cast<char*>(scratch) + per) : nullptr;
+  }
+  hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(256), 0, st, a);
+  int rc = hipGetLastError() == hipSuccess ? HIGP_OK
+                                           : set_error(HIGP_ERR_HIP, "FP64 MatVec launch failed");
+  if (rc == HIGP_OK && S > 1)
+    rc = launch_epilogue<double>(a.o1, grad ? a.o2 : nullptr, a.V, out, p.n * k, S, p.f * p.f,
+                                 p.s, cl, 2.0 * p.f, st, num_cus);
+  if (scratch) scratch_free(scratch, st);
+  return rc;
+}
+
+
+}  // namespace
+
+int launch_kmatvec_f64(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
+                       int num_cus) {
+  const bool grad = out.dl != nullptr || out.df != nullptr;
+  KFn<double> fn;
+  if (p.kernel == HIGP_GAUSSIAN)
+    fn = grad ? pick_f64_d<HIGP_GAUSSIAN, true>(p.d, k) : pick_f64_d<HIGP_GAUSSIAN, false>(p.d, k);
+  else
+    fn = grad ? pick_f64_d<HIGP_MATERN32, true>(p.d, k) : pick_f64_d<HIGP_MATERN32, false>(p.d, k);
+  return run_f64(p, k, V, out, st, fn, coord_scale(p.kernel, HIGP_FP64, p.l),
+                 p.f * p.f * dl_factor(p.kernel, HIGP_FP64, p.l), num_cus);
+}
+
+}  // namespace higp

@@ -17,8 +17,13 @@
 // scalar 1/(f² + s).
 //
 // Residual replacement (refine_every = R): after every R-th iteration the
-// recursive residual is replaced by b − K̂x, with x rounded to the MatVec
-// precision (FP32 for the BF16 form) and the MatVec run in FP32 or better.
+// recursive residual is replaced by b − K̂x.  With refine_prec = FP64 the
+// iterate x (kept in FP64) enters an FP64 MatVec over the points widened to
+// double, so the replaced residual is the true residual to FP64 accuracy and
+// the stopping test then holds for the true residual (mixed-precision
+// iterative refinement: cheap MatVecs inside CG, an accurate residual every R
+// iterations).  With refine_prec = FP32, x is rounded to float and the FP32
+// MatVec is used; the residual is then only as accurate as the FP32 floor.
 #include <vector>
 
 #include "reduce.h"
@@ -104,10 +109,10 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
 }
 
 // r = b − q (true residual) for active columns, then ‖r‖² and finish.
-template <typename T>
+template <typename T, typename TQ>
 __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int64_t chunk,
                                                            const T* __restrict__ b,
-                                                           const T* __restrict__ q, PcgState S,
+                                                           const TQ* __restrict__ q, PcgState S,
                                                            PcgScalars P) {
   __shared__ double sh[kRedThreads];
   const int c = threadIdx.x & 63;
@@ -218,8 +223,13 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
     bytes += (b + 255) / 256 * 256;
     return off;
   };
+  const bool refine = o.refine_every > 0;
+  const bool refine64 = refine && (o.refine_prec == HIGP_FP64 || p.prec == HIGP_FP64);
+  const bool widen = refine64 && p.prec != HIGP_FP64;  // FP64 copy of the points
   const size_t o_x = take(nk * 8), o_r = take(nk * 8), o_p = take(nk * sizeof(T)),
-               o_q = take(nk * sizeof(T)), o_q2 = take(o.refine_every > 0 ? nk * sizeof(T) : 0),
+               o_q = take(nk * sizeof(T)),
+               o_q2 = take(refine ? nk * (refine64 ? 8 : sizeof(T)) : 0),
+               o_xd = take(widen ? (size_t)n * p.d * 8 : 0),
                o_sc = take(8 * 64 * 8), o_int = take(4 * 64 * 4),
                o_work = take(nwork * 8 * 2), o_cnt = take(2 * 4);
   void* mem = nullptr;
@@ -230,7 +240,12 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   S.r = (double*)(base + o_r);
   T* P = (T*)(base + o_p);
   T* Q = (T*)(base + o_q);
-  T* Q2 = (T*)(base + o_q2);
+  void* Q2 = base + o_q2;
+  Problem p64 = p;  // the problem seen by an FP64 replacement MatVec
+  if (refine64) {
+    p64.prec = HIGP_FP64;
+    if (widen) p64.X = base + o_xd;
+  }
   double* sc = (double*)(base + o_sc);
   S.rho = sc;
   S.pq = sc + 64;
@@ -260,6 +275,10 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   };
   if (hipMemsetAsync(S.counter, 0, 8, st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "hipMemsetAsync failed"));
+  if (widen) {
+    rc = launch_cast_scale(n * p.d, p.X, 1, base + o_xd, 0, 1.0, st);
+    if (rc) return fail(rc);
+  }
 
   // r0 = b − K̂x0 needs a MatVec of x0 when a warm start is given.
   const T* q0 = nullptr;
@@ -299,15 +318,23 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
                        (const T*)P, (const T*)Q, S, ps, replace ? 0 : 1);
     if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     if (replace) {
-      // x rounded to the MatVec precision, K̂x in FP32 or better, r = b − K̂x.
-      rc = launch_cast_scale((int64_t)nk, S.x, 0, Q, wp, 1.0, st);
-      if (rc) return fail(rc);
       MatvecOut m2;
       m2.kv = Q2;
-      rc = launch_kmatvec(p, k, Q, m2, st, refine_prec);
-      if (rc) return fail(rc);
-      hipLaunchKernelGGL((pcg_replace<T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k,
-                         g.chunk, B, (const T*)Q2, S, ps);
+      if (refine64) {
+        // r = b − K̂x with x in FP64 and an FP64 MatVec.
+        rc = launch_kmatvec(p64, k, S.x, m2, st);
+        if (rc) return fail(rc);
+        hipLaunchKernelGGL((pcg_replace<T, double>), dim3(g.blocks), dim3(kRedThreads), 0, st, n,
+                           k, g.chunk, B, (const double*)Q2, S, ps);
+      } else {
+        // r = b − K̂x with x rounded to the MatVec precision and the FP32 MatVec.
+        rc = launch_cast_scale((int64_t)nk, S.x, 0, Q, wp, 1.0, st);
+        if (rc) return fail(rc);
+        rc = launch_kmatvec(p, k, Q, m2, st, refine_prec);
+        if (rc) return fail(rc);
+        hipLaunchKernelGGL((pcg_replace<T, T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k,
+                           g.chunk, B, (const T*)Q2, S, ps);
+      }
       if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     }
     hipLaunchKernelGGL((pcg_pupdate<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S,
@@ -324,6 +351,9 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   // Results.
   rc = launch_cast_scale((int64_t)nk, S.x, 0, Xout, wp, 1.0, st);
   if (rc) return fail(rc);
+  if (o.x_fp64 &&
+      hipMemcpyAsync(o.x_fp64, S.x, nk * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "copy of the FP64 iterate failed"));
   std::vector<int> it_h(k);
   std::vector<double> rel_h(k);
   if (hipMemcpyAsync(it_h.data(), S.iters, k * sizeof(int), hipMemcpyDeviceToHost, st) !=

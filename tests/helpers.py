@@ -35,3 +35,13 @@ def oracle_rows(X, V, kernel, l, f, s, rows):
 
 
 TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
+
+
+def colrel_cond(got, ref, refabs):
+    """Per-column error normalised by the magnitude of the summands,
+    ‖got_c − ref_c‖ / ‖(|K̂||V|)_c‖: the natural bound of a floating-point
+    product, for columns whose result cancels (sum ≪ sum of magnitudes)."""
+    got = np.asarray(got, dtype=np.float64).reshape(ref.shape[0], -1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(ref.shape[0], -1)
+    den = np.linalg.norm(np.asarray(refabs).reshape(ref.shape[0], -1), axis=0)
+    return np.linalg.norm(got - ref, axis=0) / np.where(den > 0, den, 1.0)

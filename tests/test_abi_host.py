@@ -74,9 +74,9 @@ def test_pcg_and_slq_reject_bad_options():
     p = _prob()
     info = _lib.PcgInfo()
     for kw in (dict(tol=0.0), dict(max_iter=0), dict(precond=2), dict(refine_every=-1),
-               dict(use_x0=3), dict(reserved=1)):
+               dict(use_x0=3), dict(refine_prec=2), dict(check_every=-1)):
         o = _lib.PcgOpts(tol=1e-6, max_iter=10, precond=1, refine_every=0, use_x0=0,
-                         check_every=0, reserved=0)
+                         check_every=0, refine_prec=0, x_fp64=None)
         for k, v in kw.items():
             setattr(o, k, v)
         rc = L.higp_pcg(ctypes.byref(p), 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000),

@@ -10,7 +10,7 @@ import torch
 import oracle
 import paper_2503_02259_amd as hg
 from paper_2503_02259_amd import workloads as W
-from helpers import TOL, as_prec, colrel, oracle_rows, to_dev
+from helpers import TOL, as_prec, colrel, colrel_cond, oracle_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,10 @@ def test_limits(kernel, dtype):
     V = as_prec(W.gaussian_vectors(n, 3, 77), dtype)
     Y = hg.kmatvec(to_dev(X, dtype), to_dev(V, dtype), kernel, 1e8, f, s).cpu().numpy()
     ref = f * f * np.ones((n, 1)) * V.sum(0) + s * V
-    assert colrel(Y, ref).max() <= TOL[dtype]
+    # Σ_j v_j of N(0,1) entries cancels heavily (|Σv| ≪ Σ|v|), so the error is
+    # measured against the size of the summands, f²·Σ|v| + s·|v|.
+    refabs = f * f * np.ones((n, 1)) * np.abs(V).sum(0) + s * np.abs(V)
+    assert colrel_cond(Y, ref, refabs).max() <= TOL[dtype]
     G = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1).reshape(-1, 3) * 0.1
     V2 = as_prec(W.gaussian_vectors(G.shape[0], 2, 78), dtype)
     Y2 = hg.kmatvec(to_dev(as_prec(G, dtype), dtype), to_dev(V2, dtype), kernel, 1e-3, f, s).cpu().numpy()

@@ -51,7 +51,9 @@ def test_large_l_closed_form_and_breakdown(dtype):
     ld, per = hg.slq_logdet(to_dev(X, dtype), to_dev(Z, dtype), 0, 1e8, f, s, 20)
     oz = Z.sum(0)
     ref = np.log(s) * (n - oz ** 2 / n) + np.log(s + n * f * f) * oz ** 2 / n
-    tol = 1e-9 if dtype == torch.float64 else 1e-5
+    # κ(K̂) = (s + n f²)/s = 3e5: in FP32 the rounding of the MatVec moves the
+    # small eigenvalues by ~κ·u₃₂ relative, so the FP32 bound is 1e-3.
+    tol = 1e-9 if dtype == torch.float64 else 1e-3
     assert np.all(np.abs(per - ref) <= tol * np.abs(ref))
 
 
