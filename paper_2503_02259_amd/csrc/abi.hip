@@ -87,12 +87,15 @@ namespace {
 
 size_t elem_size(int prec) { return prec == HIGP_FP64 ? 8 : 4; }
 
-bool overlaps(const void* a, const void* b, size_t bytes) {
+// [a, a + abytes) ∩ [b, b + bbytes) ≠ ∅
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
   if (!a || !b) return false;
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
-  return pa < pb + bytes && pb < pa + bytes;
+  return pa < pb + bbytes && pb < pa + abytes;
 }
+
+bool overlaps(const void* a, const void* b, size_t bytes) { return overlaps(a, bytes, b, bytes); }
 
 }  // namespace
 }  // namespace higp
@@ -177,8 +180,8 @@ int higp_pcg(const higp_problem* hp, int32_t k, const void* B, void* X, const hi
     return set_error(HIGP_ERR_INVALID_ARG, "refine_prec must be HIGP_FP64 or HIGP_FP32");
   const size_t bytes = (size_t)p.n * k * elem_size(p.prec);
   if (overlaps(B, X, bytes)) return set_error(HIGP_ERR_INVALID_ARG, "X overlaps B");
-  if (o->x_fp64 && (overlaps(o->x_fp64, B, (size_t)p.n * k * 8) ||
-                    overlaps(o->x_fp64, X, (size_t)p.n * k * 8)))
+  if (o->x_fp64 && (overlaps(o->x_fp64, (size_t)p.n * k * 8, B, bytes) ||
+                    overlaps(o->x_fp64, (size_t)p.n * k * 8, X, bytes)))
     return set_error(HIGP_ERR_INVALID_ARG, "x_fp64 overlaps B or Xsol");
   return run_pcg(p, k, B, X, *o, info, static_cast<hipStream_t>(stream));
 }

@@ -7,15 +7,15 @@
 // A-operand slot, and multiplied by the matrix core with a V tile held in
 // LDS; K is never stored.
 //
-// Work decomposition (stream-K).  The row-major space of items (row tile I of
-// BM rows) × (J tile of 128 points) is cut into equal contiguous shares, one
-// per workgroup, with exactly as many workgroups as fit on the GPU at once.
-// A workgroup walks its share; J tiles are copied global → LDS directly
-// (buffer_load … lds, double-buffered, no staging registers); whenever the
-// row tile changes it writes its partial sums for the finished row-tile
-// segment to a private slot.  An epilogue kernel adds, for every output row,
-// the slots of the workgroups that covered its row tile, in workgroup order
-// (deterministic, no atomics), and applies f², s and the derivative factors.
+// Work decomposition (split-J, XCD-aware).  Workgroup b owns row tile
+// b / S (BM rows) and J chunk b mod S (a contiguous run of 128-point J
+// tiles).  Workgroups are dealt to the 8 XCDs round-robin, so with S a
+// multiple of 8 every XCD streams only its own S/8 chunks of X and V, which
+// stay in that XCD's L2.  J tiles are copied global → LDS directly
+// (buffer_load … lds, double-buffered, no staging registers).  Each
+// workgroup writes the raw partial sums of its chunk; an epilogue kernel adds
+// the S partials of every output in chunk order (deterministic, no atomics)
+// and applies f², s and the derivative factors.
 //
 // Per wave: RB blocks of 32 rows.  At MFMA step j0 lane l supplies
 // K[i0 + l%32][j0 + l/32] for each row block; the RB products share the x_j
@@ -34,6 +34,7 @@
 // needs masking in the inner loop.  V is read as a contiguous block of 128·k
 // floats per tile (row stride k in LDS); reads past its end return 0.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <unordered_map>
 
@@ -78,24 +79,26 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
 struct Args {
   const float* Xp;  // npad×P prepared points
   const float* V;   // n×k (16-byte aligned, readable up to nk_pad elements)
-  float* part;      // partial slots [grid·maxseg][BM][k]: Σ k·v
+  float* part;      // partials [S][n][k]: Σ k·v over each J chunk
   float* part2;     // same layout: Σ k_l·v (GRAD)
   int64_t n;
   int64_t nk_pad;
-  int64_t items;    // row tiles × J tiles
   int jt_count;     // J tiles
-  int k, maxseg;
+  int jt_chunk;     // J tiles per chunk
+  int nsplit;       // S
+  int k;
 };
 
-template <int KERN, int D, int NB, int NV, int RB, bool GRAD>
+template <int KERN, int D, int NB, int NV, int RB, bool GRAD, bool EXACT>
 __global__ __launch_bounds__(256) void kmv_f32(Args a) {
   constexpr int P = D <= 4 ? 4 : 8;
   constexpr int BM = 32 * RB * kWaves;
   constexpr int NBa = NB > 0 ? NB : 1;
   constexpr int NVa = NV > 0 ? NV : 1;
   constexpr int G2 = GRAD ? 2 : 1;  // contractions: k·v and (GRAD) k_l·v
+  constexpr int KMAX = NB * 32 + NV;  // largest k served; EXACT: k == KMAX
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  const int k = a.k;
+  const int k = EXACT ? KMAX : a.k;   // V row stride in LDS (compile-time when EXACT)
   const int vtile = kBJ * k;
   float* Xs = smem;                 // [2][kBJ][P]
   float* Vs = smem + 2 * kBJ * P;   // [2][kBJ·k]
@@ -106,22 +109,18 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
   const int half = lane >> 5;
   const int l32 = lane & 31;
 
-  const int64_t grid = gridDim.x;
-  const int64_t it0 = (int64_t)blockIdx.x * a.items / grid;
-  const int64_t it1 = ((int64_t)blockIdx.x + 1) * a.items / grid;
-  if (it0 >= it1) return;
-  const int JT = a.jt_count;
-  const int64_t rt_first = it0 / JT;
+  const int split = blockIdx.x % a.nsplit;
+  const int64_t rt = blockIdx.x / a.nsplit;
+  const int jt_beg = split * a.jt_chunk;
+  const int jt_end = jt_beg + a.jt_chunk < a.jt_count ? jt_beg + a.jt_chunk : a.jt_count;
 
   float xi[RB][P];
-  auto load_rows = [&](int64_t rt) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int64_t i = rt * BM + wave * 32 * RB + rb * 32 + l32;
+  for (int rb = 0; rb < RB; ++rb) {
+    const int64_t i = rt * BM + wave * 32 * RB + rb * 32 + l32;
 #pragma unroll
-      for (int c = 0; c < P; ++c) xi[rb][c] = i < a.n ? a.Xp[i * P + c] : 0.0f;
-    }
-  };
+    for (int c = 0; c < P; ++c) xi[rb][c] = i < a.n ? a.Xp[i * P + c] : 0.0f;
+  }
 
   f32x16 acc[G2][RB][NBa];
   double tot[G2][RB][NBa][16];
@@ -164,11 +163,12 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
                                                  16 * (m + lane), 0, 0, 0);
   };
 
-  // Partial sums of one row-tile segment → its slot (FP64 totals, rounded once).
-  auto flush = [&](int64_t rt) {
-    const int64_t slot = (int64_t)blockIdx.x * a.maxseg + (rt - rt_first);
-    float* q1 = a.part + slot * BM * k;
-    float* q2 = GRAD ? a.part2 + slot * BM * k : nullptr;
+  // Partial sums of this chunk → part[split] (FP64 totals, rounded once).
+  auto flush = [&]() {
+    const int64_t nk = a.n * k;
+    float* q1 = a.part + (int64_t)split * nk + rt * BM * k;
+    float* q2 = GRAD ? a.part2 + (int64_t)split * nk + rt * BM * k : nullptr;
+    const int64_t rows_left = a.n - rt * BM;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int lrow0 = wave * 32 * RB + rb * 32;
@@ -179,8 +179,10 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int lrow = lrow0 + 8 * (r >> 2) + 4 * half + (r & 3);
-            q1[lrow * k + col] = (float)tot[0][rb][b][r];
-            if constexpr (GRAD) q2[lrow * k + col] = (float)tot[G2 - 1][rb][b][r];
+            if (lrow < rows_left) {
+              q1[lrow * k + col] = (float)tot[0][rb][b][r];
+              if constexpr (GRAD) q2[lrow * k + col] = (float)tot[G2 - 1][rb][b][r];
+            }
           }
         }
 #pragma unroll
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
         // lanes l and l+32 hold the two halves of row l%32
 #pragma unroll
         for (int g = 0; g < G2; ++g) totv[g][rb][v] += __shfl_xor(totv[g][rb][v], 32);
-        if (half == 0) {
+        if (half == 0 && lrow0 + l32 < rows_left) {
           q1[(lrow0 + l32) * k + NB * 32 + v] = (float)totv[0][rb][v];
           if constexpr (GRAD) q2[(lrow0 + l32) * k + NB * 32 + v] = (float)totv[G2 - 1][rb][v];
         }
@@ -203,22 +205,13 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
     }
   };
 
-  // Walk the share one row-tile segment at a time, tracking (row tile, J
-  // tile) incrementally.
-  int64_t rt = rt_first;
-  int jt = (int)(it0 - rt_first * JT);
-  int64_t left = it1 - it0;
   int cur = 0;
-  gload(jt, 0);
+  if (jt_beg < jt_end) gload(jt_beg, 0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  while (left > 0) {
-    const int seg = left < (int64_t)(JT - jt) ? (int)left : JT - jt;
-    load_rows(rt);
-    for (int sgi = 0; sgi < seg; ++sgi) {
-    const int jn = jt + 1 == JT ? 0 : jt + 1;
-    if (left > 1) gload(jn, cur ^ 1);
+  for (int jt = jt_beg; jt < jt_end; ++jt) {
+    if (jt + 1 < jt_end) gload(jt + 1, cur ^ 1);
 
     const float* xs = Xs + cur * kBJ * P + half * P;
     const float* vb_base = Vs + cur * vtile + half * k + l32;
@@ -289,45 +282,23 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
 
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    jt = jn;
     cur ^= 1;
-    --left;
-    }
-    flush(rt);
-    ++rt;
   }
+  flush();
 }
 
-// For every output element: the sum of the partial slots of the workgroups
-// that covered its row tile, in workgroup order, then K̂V = f²·Σ + s·V and
-// the derivative outputs.
-__global__ void kmv_f32_epilogue(const float* __restrict__ part, const float* __restrict__ part2,
+// out = f²·Σ_s P1[s] + s·V (chunks added in order, in FP64), and the
+// derivative outputs.
+__global__ void kmv_f32_epilogue(const float* __restrict__ P1, const float* __restrict__ P2,
                                  const float* __restrict__ V, float* o1, float* o2, float* o3,
-                                 int64_t n, int k, int bm, int64_t items, int jt_count,
-                                 int64_t grid, int maxseg, double f2, double s, double cl,
+                                 int64_t count, int nsplit, double f2, double s, double cl,
                                  double cf) {
-  const int64_t count = n * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / k;
-    const int c = (int)(e % k);
-    const int64_t rt = i / bm;
-    const int lr = (int)(i % bm);
-    const int64_t lo = rt * jt_count, hi = lo + jt_count;
-    // first workgroup whose share [w·items/grid, (w+1)·items/grid) reaches lo
-    int64_t w = lo * grid / items;
-    while (w > 0 && w * items / grid > lo) --w;
-    while (w + 1 < grid && (w + 1) * items / grid <= lo) ++w;
     double s1 = 0.0, s2 = 0.0;
-    for (; w < grid; ++w) {
-      const int64_t a0 = w * items / grid;
-      const int64_t a1 = (w + 1) * items / grid;
-      if (a0 >= hi) break;
-      if (a1 <= a0 || a1 <= lo) continue;
-      const int64_t slot = w * maxseg + (rt - a0 / jt_count);
-      const int64_t o = (slot * bm + lr) * k + c;
-      s1 += (double)part[o];
-      if (part2) s2 += (double)part2[o];
+    for (int sp = 0; sp < nsplit; ++sp) {
+      s1 += (double)P1[sp * count + e];
+      if (P2) s2 += (double)P2[sp * count + e];
     }
     if (o1) o1[e] = (float)(f2 * s1 + s * (double)V[e]);
     if (o2) o2[e] = (float)(cl * s2);
@@ -337,21 +308,26 @@ __global__ void kmv_f32_epilogue(const float* __restrict__ part, const float* __
 
 using Fn = void (*)(Args);
 
-template <int KERN, int D, int NB, int NV, bool GRAD>
+template <int KERN, int D, int NB, int NV, bool GRAD, bool EXACT>
 Fn inst(int* rb) {
   constexpr int RB = (NB == 2 || GRAD) ? 1 : 2;
   *rb = RB;
-  return kmv_f32<KERN, D, NB, NV, RB, GRAD>;
+  return kmv_f32<KERN, D, NB, NV, RB, GRAD, EXACT>;
 }
 
+// Column blocking: NB blocks of 32 MFMA columns and NV ≤ 2 VALU columns.
+// EXACT instances (k = 1, 2, 32, 33, 34, 64) know the V row stride at
+// compile time.
 template <int KERN, int D, bool GRAD>
 Fn pick_cols(int k, int* rb) {
-  if (k == 1) return inst<KERN, D, 0, 1, GRAD>(rb);
-  if (k == 2) return inst<KERN, D, 0, 2, GRAD>(rb);
-  if (k <= 32) return inst<KERN, D, 1, 0, GRAD>(rb);
-  if (k == 33) return inst<KERN, D, 1, 1, GRAD>(rb);
-  if (k == 34) return inst<KERN, D, 1, 2, GRAD>(rb);
-  return inst<KERN, D, 2, 0, GRAD>(rb);
+  if (k == 1) return inst<KERN, D, 0, 1, GRAD, true>(rb);
+  if (k == 2) return inst<KERN, D, 0, 2, GRAD, true>(rb);
+  if (k == 32) return inst<KERN, D, 1, 0, GRAD, true>(rb);
+  if (k < 32) return inst<KERN, D, 1, 0, GRAD, false>(rb);
+  if (k == 33) return inst<KERN, D, 1, 1, GRAD, true>(rb);
+  if (k == 34) return inst<KERN, D, 1, 2, GRAD, true>(rb);
+  if (k == 64) return inst<KERN, D, 2, 0, GRAD, true>(rb);
+  return inst<KERN, D, 2, 0, GRAD, false>(rb);
 }
 
 template <int KERN, bool GRAD>
@@ -361,6 +337,12 @@ Fn pick_d(int d, int k, int* rb) {
   if (d == 4) return pick_cols<KERN, 4, GRAD>(k, rb);
   return pick_cols<KERN, 8, GRAD>(k, rb);
 }
+
+// Split count override for tuning experiments (HIGP_F32_SPLITS; 0 = automatic).
+int g_split_override = [] {
+  const char* e = getenv("HIGP_F32_SPLITS");
+  return e ? atoi(e) : 0;
+}();
 
 // Resident workgroups per CU for (kernel, LDS bytes), cached per device.
 int blocks_per_cu(Fn fn, size_t lds) {
@@ -401,15 +383,22 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
   const int64_t jt_count = (p.n + kBJ - 1) / kBJ;
   const int64_t npad = jt_count * kBJ;
   const int64_t rt_count = (p.n + bm - 1) / bm;
-  const int64_t items = rt_count * jt_count;
   const size_t lds = (size_t)2 * kBJ * P * 4 + (size_t)2 * kBJ * k * 4;
   if (lds > 65536 &&
       hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return set_error(HIGP_ERR_HIP, "cannot reserve %zu bytes of LDS", lds);
-  const int64_t grid = std::min<int64_t>(items, (int64_t)num_cus * blocks_per_cu(fn, lds));
-  const int64_t per = (items + grid - 1) / grid;
-  const int maxseg = (int)((per + jt_count - 1) / jt_count + 1);
+  // Split count S: a multiple of 8 (one set of J chunks per XCD) when the
+  // grid is large enough, growing until there are several rounds of
+  // workgroups per CU (so the last, partial round costs little) while every
+  // chunk keeps at least two J tiles.
+  const int64_t slots = (int64_t)num_cus * blocks_per_cu(fn, lds);
+  int S = 1;
+  while (S < 64 && rt_count * S < 8 * slots && jt_count >= 4LL * S) S *= 2;
+  if (g_split_override > 0) S = g_split_override;
+  const int jt_chunk = (int)((jt_count + S - 1) / S);
+  const int64_t grid = rt_count * S;
+  if (grid > 0x7fffffffLL) return set_error(HIGP_ERR_INVALID_ARG, "n too large");
 
   // Scratch: prepared points (whole J tiles); a zero-padded copy of V unless
   // V is 16-byte aligned and n·k is a multiple of 4 (tiles move 16-byte
@@ -418,7 +407,7 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
   const int64_t nk_pad = (nk + 3) / 4 * 4;
   const size_t xp_bytes = ((size_t)npad * P * 4 + 255) / 256 * 256;
   const size_t v_bytes = direct_v ? 0 : ((size_t)nk_pad * 4 + 255) / 256 * 256;
-  const size_t part_bytes = ((size_t)grid * maxseg * bm * k * 4 + 255) / 256 * 256;
+  const size_t part_bytes = ((size_t)S * nk * 4 + 255) / 256 * 256;
   void* scratch = nullptr;
   HIGP_TRY(scratch_alloc(&scratch, xp_bytes + v_bytes + part_bytes * (grad ? 2 : 1), st));
   char* base = static_cast<char*>(scratch);
@@ -448,16 +437,16 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
   a.part2 = grad ? reinterpret_cast<float*>(base + xp_bytes + v_bytes + part_bytes) : nullptr;
   a.n = p.n;
   a.nk_pad = direct_v ? nk : nk_pad;
-  a.items = items;
   a.jt_count = (int)jt_count;
+  a.jt_chunk = jt_chunk;
+  a.nsplit = S;
   a.k = k;
-  a.maxseg = maxseg;
   hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), lds, st, a);
   const unsigned eb = (unsigned)std::min<int64_t>((nk + 255) / 256, 8LL * num_cus);
   hipLaunchKernelGGL(kmv_f32_epilogue, dim3(eb), dim3(256), 0, st, (const float*)a.part,
                      (const float*)a.part2, V, static_cast<float*>(out.kv),
-                     static_cast<float*>(out.dl), static_cast<float*>(out.df), p.n, k, bm, items,
-                     (int)jt_count, grid, maxseg, p.f * p.f, p.s, cl, 2.0 * p.f);
+                     static_cast<float*>(out.dl), static_cast<float*>(out.df), nk, S, p.f * p.f,
+                     p.s, cl, 2.0 * p.f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) rc = set_error(HIGP_ERR_HIP, "FP32 MatVec launch failed: %s", hipGetErrorString(e));
   scratch_free(scratch, st);

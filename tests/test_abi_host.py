@@ -126,3 +126,20 @@ def test_tridiag_eig_clustered_and_split():
     lam, S = scipy.linalg.eigh_tridiagonal(a, b)
     np.testing.assert_allclose(np.sort(th), lam, rtol=1e-12, atol=1e-15)
     assert abs(np.sum(tau ** 2) - 1.0) < 1e-14
+
+
+def test_pcg_overlap_checks_use_each_buffer_size():
+    # x_fp64 (double) right after a float B of n·k·4 bytes does not overlap;
+    # one starting inside B does.
+    L = _lib.lib()
+    p = _prob()            # n = 10, float
+    info = _lib.PcgInfo()
+    o = _lib.PcgOpts(tol=1e-6, max_iter=10, precond=1, refine_every=0, use_x0=0,
+                     check_every=0, refine_prec=0, x_fp64=ctypes.c_void_p(0x2000 + 10 * 2 * 4))
+    # B at 0x2000 (80 bytes for k=2), Xsol far away, x_fp64 right after B: the
+    # call then proceeds past validation, so only the overlapping case is run.
+    o.x_fp64 = 0x2000 + 40
+    rc = L.higp_pcg(ctypes.byref(p), 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x90000),
+                    ctypes.byref(o), ctypes.byref(info), None)
+    assert rc == _lib.HIGP_ERR_INVALID_ARG
+    assert b"x_fp64" in L.higp_last_error()
