@@ -23,13 +23,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_MFMA_FP32 = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
+PROFILE = os.path.join(ROOT, "profiles", "kmv_f32_gauss_n100000_k33.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2503_02259_amd", "csrc", "kmatvec_f32.hip")
 
 
-def cpu_baseline(prob, rows=12288, workers=None):
+def measured_traffic():
+    """HBM bytes per launch of the FP32 MatVec kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(PROFILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in txt.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "source_sha256_16: ")))
+    if vals.get("source_sha256_16", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(prob, rows=None, workers=None):
     """Time the oracle MatVec on the first `rows` rows (all n columns)."""
     import oracle
     from threadpoolctl import threadpool_limits
     X, V = prob.X.astype(np.float32).astype(np.float64), prob.extra["V"].astype(np.float32).astype(np.float64)
+    rows = min(rows or X.shape[0], X.shape[0])
     workers = workers or min(16, os.cpu_count() or 1)
     Xs = X  # all n points as columns; only `rows` rows of K̂ are formed
     n = X.shape[0]
@@ -59,7 +79,10 @@ def main():
     ap.add_argument("--kernel", default="gaussian", choices=["gaussian", "matern32"])
     ap.add_argument("--no-solve", action="store_true", help="skip the PCG/SLQ wall-time legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rows", type=int, default=12288)
+    ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the CPU oracle sample (0 = all)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of this many MiB first (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; the multi-GPU path is not built "
@@ -79,6 +102,12 @@ def main():
     Y = torch.empty_like(V)
     stream = torch.cuda.current_stream(dev)
 
+    if args.calib_copy > 0:
+        src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         hg.kmatvec(X, V, kern, prob.l, prob.f, prob.s, out=Y)
     torch.cuda.synchronize()
@@ -113,7 +142,8 @@ def main():
                                "f=1 l=0.1 s=1e-2, V=[y|32 Rademacher] k=33, FP32" % args.kernel,
                    "n": n, "d": 3, "k": k, "kernel": args.kernel, "precision": "fp32"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_MFMA_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_FP32, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_FP32,
+                     "traffic": measured_traffic() if kern == hg.GAUSSIAN else None},
         "wall_s_timed": wall,
     }
 
@@ -137,7 +167,7 @@ def main():
         out["slq_stderr"] = float(per.std(ddof=1) / np.sqrt(per.size))
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
 
 
