@@ -150,6 +150,43 @@ int higp_slq_logdet(const higp_problem* p, int32_t nprobe, int32_t nsteps,
                     int32_t precond, double* logdet, double* per_probe,
                     void* stream);
 
+/* Column dot products out[c] = Σ_i A[i,c]·B[i,c] of two device n×k blocks,
+ * accumulated in FP64 in a fixed order (bitwise reproducible).  prec_a and
+ * prec_b give each block's element type (HIGP_FP64 = double, otherwise
+ * float).  out: host array of k doubles.  1 ≤ k ≤ HIGP_MAX_K, n ≥ 1.
+ * Synchronises `stream`.  (The inner products of the gradient of the
+ * negative log marginal likelihood, "Gaussian Processes".)               */
+int higp_coldot(int64_t n, int32_t k, int32_t prec_a, const void* A, int32_t prec_b,
+                const void* B, double* out, void* stream);
+
+/* Options of higp_nlml.                                                    */
+typedef struct {
+  double tol;           /* PCG tolerance on [y | Z] (tracked residual) */
+  int32_t max_iter;     /* PCG iteration cap */
+  int32_t precond;      /* 0 = none, 1 = Jacobi (also used for eq. (1) and (2)) */
+  int32_t refine_every; /* PCG residual replacement period (0 = off), FP64 MatVec */
+  int32_t nsteps;       /* Lanczos steps of SLQ */
+  int32_t reorth;       /* 1 = full reorthogonalisation in SLQ */
+  int32_t reserved;     /* must be 0 */
+} higp_nlml_opts;
+
+/* Negative log marginal likelihood L(Θ) = ½(yᵀK̂⁻¹y + log|K̂| + n·log 2π) and
+ * its gradient ∂L/∂θ = ½(−yᵀK̂⁻¹(∂K̂/∂θ)K̂⁻¹y + tr(K̂⁻¹ ∂K̂/∂θ)) for
+ * θ = (l, f, s) ("Gaussian Processes"), estimated as in the paper:
+ *   K̂⁻¹y and K̂⁻¹Z by PCG on [y | Z] (one MatVec of 1 + nprobe columns per
+ *   iteration); log|K̂| by eq. (1) with SLQ over the probes Z; the trace by
+ *   eq. (2) with M = diag(K̂) and the Hutchinson estimator
+ *   (1/N) Σ_i [(K̂⁻¹z_i)ᵀ(∂K̂/∂θ z_i) − z_iᵀM⁻¹(∂M/∂θ)z_i]; the products
+ *   ∂K̂/∂θ·[K̂⁻¹y | Z] by one fused derivative MatVec.
+ * y: device n; Z: device n×nprobe (both in the problem's element type);
+ * 1 ≤ nprobe ≤ HIGP_MAX_K − 1.  loss: host double; grad: host double[3]
+ * (∂L/∂l, ∂L/∂f, ∂L/∂s); logdet: host double or NULL (the SLQ estimate);
+ * pcg_iters: host int32 or NULL (largest PCG iteration count).
+ * Synchronises `stream`.                                                  */
+int higp_nlml(const higp_problem* p, const void* y, int32_t nprobe, const void* Z,
+              const higp_nlml_opts* opts, double* loss, double* grad, double* logdet,
+              int32_t* pcg_iters, void* stream);
+
 /* Host utility: eigenvalues θ[0..m-1] and first eigenvector components
  * τ[0..m-1] of the symmetric tridiagonal T with diagonal a[0..m-1] and
  * off-diagonal b[0..m-2] — the FP64 eigen-solve inside higp_slq_logdet

@@ -11,7 +11,11 @@ from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, HigpError  # noqa: F401
 def __getattr__(name):
     # Import the torch-facing API lazily so that `workloads` and the build
     # script can be used without importing torch.
-    if name in ("kmatvec", "kmatvec_grad", "pcg", "slq_logdet", "tridiag_eig", "problem"):
+    if name in ("kmatvec", "kmatvec_grad", "pcg", "slq_logdet", "tridiag_eig", "problem",
+                "coldot", "nlml"):
         from . import api
         return getattr(api, name)
+    if name in ("KMatVecFn", "GPLossFn", "GPRModel"):
+        from . import autograd
+        return getattr(autograd, name)
     raise AttributeError(name)

@@ -22,8 +22,9 @@ FP32 = 1
 BF16 = 2
 
 # Every symbol declared in include/higp.h.
-EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
-           "higp_tridiag_eig", "higp_error_string", "higp_last_error", "higp_version")
+EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet", "higp_coldot",
+           "higp_nlml", "higp_tridiag_eig", "higp_error_string", "higp_last_error",
+           "higp_version")
 
 
 class Problem(ctypes.Structure):
@@ -43,6 +44,13 @@ class PcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)),
                 ("relres", ctypes.POINTER(ctypes.c_double)),
                 ("converged", ctypes.POINTER(ctypes.c_int32))]
+
+
+class NlmlOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
+                ("nsteps", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class HigpError(RuntimeError):
@@ -72,13 +80,16 @@ def lib():
         L.higp_pcg.argtypes = [PP, i32, vp, vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), vp]
         L.higp_slq_logdet.argtypes = [PP, i32, i32, vp, ctypes.c_uint64, i32, i32, dp, dp, vp]
         L.higp_tridiag_eig.argtypes = [i32, dp, dp, dp, dp]
+        L.higp_coldot.argtypes = [i64, i32, i32, vp, i32, vp, dp, vp]
+        L.higp_nlml.argtypes = [PP, vp, i32, vp, ctypes.POINTER(NlmlOpts), dp, dp, dp,
+                                ctypes.POINTER(ctypes.c_int32), vp]
         L.higp_error_string.argtypes = [ctypes.c_int]
         L.higp_error_string.restype = ctypes.c_char_p
         L.higp_last_error.argtypes = []
         L.higp_last_error.restype = ctypes.c_char_p
         L.higp_version.argtypes = []
         for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
-                     "higp_tridiag_eig", "higp_version"):
+                     "higp_coldot", "higp_nlml", "higp_tridiag_eig", "higp_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -173,3 +173,46 @@ def tridiag_eig(a, b):
                                           b.ctypes.data_as(dp) if b.size else None,
                                           th.ctypes.data_as(dp), tau.ctypes.data_as(dp)))
     return th, tau
+
+
+def coldot(A, B, stream=None):
+    """Column dot products Σ_i A[i,c]·B[i,c] (FP64, deterministic) of two
+    device n×k blocks (float32 or float64 each).  Returns a numpy array."""
+    A2 = A.unsqueeze(1) if A.dim() == 1 else A
+    B2 = B.unsqueeze(1) if B.dim() == 1 else B
+    if A2.shape != B2.shape:
+        raise ValueError("shape mismatch %s vs %s" % (tuple(A2.shape), tuple(B2.shape)))
+    n, k = A2.shape
+    pa = FP64 if A2.dtype == torch.float64 else FP32
+    pb = FP64 if B2.dtype == torch.float64 else FP32
+    ap = _dev(A2, "A", A2.dtype)
+    bp = _dev(B2, "B", B2.dtype)
+    out = np.zeros(k, dtype=np.float64)
+    _lib.check(_lib.lib().higp_coldot(n, k, pa, ap, pb, bp,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _stream(stream, A2.device)))
+    return out
+
+
+def nlml(X, y, Z, kernel, l, f, s, tol=1e-6, max_iter=2000, precond="jacobi", refine_every=0,
+         nsteps=50, reorth=True, precision=None, stream=None):
+    """L(Θ) and (∂L/∂l, ∂L/∂f, ∂L/∂s) by PCG on [y | Z], SLQ over Z and the
+    Hutchinson estimator (eq. (1) and (2)).  Returns (loss, grad, info)."""
+    p = problem(X, kernel, l, f, s, precision)
+    n, N = Z.shape
+    yp = _dev(y, "y", X.dtype, (p.n,))
+    zp = _dev(Z, "Z", X.dtype, (p.n, N))
+    o = _lib.NlmlOpts(tol=float(tol), max_iter=int(max_iter),
+                      precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
+                      refine_every=int(refine_every), nsteps=int(nsteps),
+                      reorth=1 if reorth else 0, reserved=0)
+    loss = ctypes.c_double()
+    logdet = ctypes.c_double()
+    its = ctypes.c_int32()
+    grad = np.zeros(3, dtype=np.float64)
+    _lib.check(_lib.lib().higp_nlml(ctypes.byref(p), yp, N, zp, ctypes.byref(o),
+                                   ctypes.byref(loss),
+                                   grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(logdet), ctypes.byref(its),
+                                   _stream(stream, X.device)))
+    return loss.value, grad, dict(logdet=logdet.value, pcg_iters=its.value)

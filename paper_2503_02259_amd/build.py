@@ -15,8 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhigp.so")
-SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f64.hip", "blas.hip", "pcg.hip",
-           "slq.hip"]
+SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f64.hip", "kmatvec_bf16.hip",
+           "blas.hip", "pcg.hip", "slq.hip", "nlml.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -24,6 +24,9 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
     # Keep the compiler from forming packed-FP32 (v_pk_*_f32) instructions.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: results feed VALU code directly,
+    # without v_accvgpr_read copies.
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
 

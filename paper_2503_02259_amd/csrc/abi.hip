@@ -12,6 +12,10 @@ int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts
             higp_pcg_info* info, hipStream_t st);
 int run_slq(const Problem& p, int N, int m, const void* Z, int reorth, int precond,
             double* logdet, double* per_probe, hipStream_t st);
+int run_nlml(const Problem& p, const void* y, int N, const void* Z, const higp_nlml_opts& o,
+             double* loss, double* grad, double* logdet, int32_t* iters, hipStream_t st);
+int host_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, double* out,
+                hipStream_t st);
 
 namespace {
 thread_local char g_msg[512] = "";
@@ -203,6 +207,40 @@ int higp_slq_logdet(const higp_problem* hp, int32_t nprobe, int32_t nsteps, cons
   if (!Z) return set_error(HIGP_ERR_UNSUPPORTED, "Z = NULL (device-generated probes) is not supported");
   return run_slq(p, nprobe, nsteps, Z, reorth, precond, logdet, per_probe,
                  static_cast<hipStream_t>(stream));
+}
+
+int higp_coldot(int64_t n, int32_t k, int32_t prec_a, const void* A, int32_t prec_b,
+                const void* B, double* out, void* stream) {
+  clear_error();
+  if (n < 1 || n > (int64_t(1) << 30))
+    return set_error(HIGP_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (k < 1 || k > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
+  for (int pr : {prec_a, prec_b})
+    if (pr != HIGP_FP64 && pr != HIGP_FP32 && pr != HIGP_BF16)
+      return set_error(HIGP_ERR_INVALID_ARG, "unknown precision %d", pr);
+  if (!A || !B || !out) return set_error(HIGP_ERR_INVALID_ARG, "A, B and out must be non-NULL");
+  return host_coldot(n, k, A, prec_a == HIGP_FP64 ? 0 : 1, B, prec_b == HIGP_FP64 ? 0 : 1, out,
+                     static_cast<hipStream_t>(stream));
+}
+
+int higp_nlml(const higp_problem* hp, const void* y, int32_t nprobe, const void* Z,
+              const higp_nlml_opts* o, double* loss, double* grad, double* logdet,
+              int32_t* pcg_iters, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (nprobe < 1 || nprobe > HIGP_MAX_K - 1)
+    return set_error(HIGP_ERR_INVALID_ARG, "nprobe = %d out of range [1, %d]", nprobe,
+                     HIGP_MAX_K - 1);
+  if (!y || !Z || !o || !loss || !grad)
+    return set_error(HIGP_ERR_INVALID_ARG, "y, Z, opts, loss and grad must be non-NULL");
+  if (!(o->tol > 0.0) || o->max_iter < 1 || (o->precond != 0 && o->precond != 1) ||
+      o->refine_every < 0 || o->nsteps < 1 || o->nsteps > 1024 ||
+      (o->reorth != 0 && o->reorth != 1) || o->reserved != 0)
+    return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
+  return run_nlml(p, y, nprobe, Z, *o, loss, grad, logdet, pcg_iters,
+                  static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

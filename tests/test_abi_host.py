@@ -143,3 +143,27 @@ def test_pcg_overlap_checks_use_each_buffer_size():
                     ctypes.byref(o), ctypes.byref(info), None)
     assert rc == _lib.HIGP_ERR_INVALID_ARG
     assert b"x_fp64" in L.higp_last_error()
+
+
+def test_coldot_and_nlml_reject_bad_arguments():
+    L = _lib.lib()
+    out = (ctypes.c_double * 4)()
+    assert L.higp_coldot(0, 2, 0, ctypes.c_void_p(16), 0, ctypes.c_void_p(32), out, None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_coldot(10, 65, 0, ctypes.c_void_p(16), 0, ctypes.c_void_p(32), out, None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_coldot(10, 2, 7, ctypes.c_void_p(16), 0, ctypes.c_void_p(32), out, None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_coldot(10, 2, 0, None, 0, ctypes.c_void_p(32), out, None) == _lib.HIGP_ERR_INVALID_ARG
+    p = _prob()
+    loss = ctypes.c_double()
+    g = (ctypes.c_double * 3)()
+    good = dict(tol=1e-6, max_iter=10, precond=1, refine_every=0, nsteps=10, reorth=1, reserved=0)
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=3), dict(refine_every=-1),
+                dict(nsteps=0), dict(nsteps=5000), dict(reorth=2), dict(reserved=1)):
+        o = _lib.NlmlOpts(**{**good, **bad})
+        rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), 4, ctypes.c_void_p(64),
+                         ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG, bad
+    o = _lib.NlmlOpts(**good)
+    for N in (0, 64):
+        rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), N, ctypes.c_void_p(64),
+                         ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG
