@@ -187,6 +187,74 @@ int higp_nlml(const higp_problem* p, const void* y, int32_t nprobe, const void* 
               const higp_nlml_opts* opts, double* loss, double* grad, double* logdet,
               int32_t* pcg_iters, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching serving of independent GP solves (FP32 form).
+ *
+ * A request is one problem K̂ = f²·k(X,X;l) + s·I with targets y and probes
+ * Z; the server computes x = K̂⁻¹y by Jacobi-preconditioned CG (tolerance on
+ * the recursive residual, as higp_pcg) and log|K̂| by eq. (1) with SLQ over
+ * the probes (full reorthogonalisation, as higp_slq_logdet) — the two terms of
+ * L(Θ) ("Gaussian Processes").  Requests wait in a FIFO queue and are admitted
+ * while a slot is free and their device state fits in hbm_budget; admitted
+ * requests keep their state resident.  Each higp_server_step runs one round:
+ * admissions, ONE batched MatVec launch for every active request (the CG
+ * column and the live Lanczos columns of a request, k ≤ 32), every request's
+ * CG and Lanczos updates, and retirement of finished requests.  A request's
+ * arithmetic depends only on the request, so its results are bitwise equal
+ * alone and in any mix.  All work is ordered on opts.stream; higp_server_step
+ * synchronises it.  A server is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct higp_server higp_server;  /* opaque */
+
+typedef struct {
+  uint64_t hbm_budget; /* bytes of device memory the server may hold for request state */
+  int32_t max_active;  /* concurrently active requests, 1..4096 */
+  int32_t reserved;    /* must be 0 */
+  void* stream;        /* hipStream_t (NULL = default stream) */
+} higp_server_opts;
+
+typedef struct {
+  higp_problem p;      /* prec must be HIGP_FP32; X device n×d float */
+  const void* y;       /* device n float */
+  const void* Z;       /* device n×nprobe float (±1 probes), NULL if nprobe = 0 */
+  int32_t nprobe;      /* 0..31 */
+  int32_t nsteps;      /* Lanczos steps (1..1024) when nprobe > 0 */
+  double tol;          /* CG tolerance (> 0) */
+  int32_t max_iter;    /* CG iteration cap (≥ 1) */
+  int32_t reserved;    /* must be 0 */
+  void* x_out;         /* device n float: receives x = K̂⁻¹y when the request is done */
+} higp_request;
+
+#define HIGP_REQ_QUEUED 0
+#define HIGP_REQ_ACTIVE 1
+#define HIGP_REQ_DONE 2
+#define HIGP_REQ_FAILED 3
+
+typedef struct {
+  int32_t state;         /* HIGP_REQ_* */
+  int32_t iters;         /* CG iterations */
+  double relres;         /* final recursive relative residual */
+  int32_t converged;     /* relres ≤ tol */
+  int32_t lanczos_steps; /* shortest Lanczos run over the probes */
+  double logdet;         /* SLQ estimate of log|K̂| (NaN if nprobe = 0) */
+  int32_t rounds;        /* server rounds the request took part in */
+  int32_t reserved;
+} higp_request_status;
+
+/* Device bytes the server reserves for a request (state, vectors, Lanczos
+ * basis, batch partials).  Host only; 0 for invalid sizes.                  */
+uint64_t higp_request_footprint(int64_t n, int32_t d, int32_t nprobe, int32_t nsteps);
+
+int higp_server_create(const higp_server_opts* opts, higp_server** server);
+/* Queue a request; the caller's buffers (X, y, Z, x_out) must stay valid until
+ * the request is done.  HIGP_ERR_OOM if it can never fit in the budget.      */
+int higp_server_submit(higp_server* server, const higp_request* req, int64_t* id);
+/* One round (see above); returns the numbers of active and queued requests. */
+int higp_server_step(higp_server* server, int32_t* n_active, int32_t* n_queued);
+int higp_server_status(higp_server* server, int64_t id, higp_request_status* status);
+/* Frees all server memory (active requests are abandoned).                  */
+int higp_server_destroy(higp_server* server);
+
 /* Host utility: eigenvalues θ[0..m-1] and first eigenvector components
  * τ[0..m-1] of the symmetric tridiagonal T with diagonal a[0..m-1] and
  * off-diagonal b[0..m-2] — the FP64 eigen-solve inside higp_slq_logdet

@@ -23,8 +23,11 @@ BF16 = 2
 
 # Every symbol declared in include/higp.h.
 EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet", "higp_coldot",
-           "higp_nlml", "higp_tridiag_eig", "higp_error_string", "higp_last_error",
-           "higp_version")
+           "higp_nlml", "higp_request_footprint", "higp_server_create", "higp_server_submit",
+           "higp_server_step", "higp_server_status", "higp_server_destroy", "higp_tridiag_eig",
+           "higp_error_string", "higp_last_error", "higp_version")
+
+HIGP_REQ_QUEUED, HIGP_REQ_ACTIVE, HIGP_REQ_DONE, HIGP_REQ_FAILED = 0, 1, 2, 3
 
 
 class Problem(ctypes.Structure):
@@ -50,6 +53,25 @@ class NlmlOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
                 ("nsteps", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("p", Problem), ("y", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+                ("nprobe", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x_out", ctypes.c_void_p)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("iters", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("converged", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("logdet", ctypes.c_double), ("rounds", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -81,6 +103,13 @@ def lib():
         L.higp_slq_logdet.argtypes = [PP, i32, i32, vp, ctypes.c_uint64, i32, i32, dp, dp, vp]
         L.higp_tridiag_eig.argtypes = [i32, dp, dp, dp, dp]
         L.higp_coldot.argtypes = [i64, i32, i32, vp, i32, vp, dp, vp]
+        L.higp_request_footprint.argtypes = [i64, i32, i32, i32]
+        L.higp_request_footprint.restype = ctypes.c_uint64
+        L.higp_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.higp_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]
+        L.higp_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.higp_server_status.argtypes = [vp, i64, ctypes.POINTER(RequestStatus)]
+        L.higp_server_destroy.argtypes = [vp]
         L.higp_nlml.argtypes = [PP, vp, i32, vp, ctypes.POINTER(NlmlOpts), dp, dp, dp,
                                 ctypes.POINTER(ctypes.c_int32), vp]
         L.higp_error_string.argtypes = [ctypes.c_int]
@@ -89,7 +118,9 @@ def lib():
         L.higp_last_error.restype = ctypes.c_char_p
         L.higp_version.argtypes = []
         for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
-                     "higp_coldot", "higp_nlml", "higp_tridiag_eig", "higp_version"):
+                     "higp_coldot", "higp_nlml", "higp_tridiag_eig", "higp_version",
+                     "higp_server_create", "higp_server_submit", "higp_server_step",
+                     "higp_server_status", "higp_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

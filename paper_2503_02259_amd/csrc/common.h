@@ -68,6 +68,23 @@ struct MatvecOut {
 int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                    int prec_override = -1);
 
+// One problem of a batched FP32 MatVec (serving): prepared points (see
+// prepare_points_f32), V n×k (16-byte aligned, zero up to n·k rounded up to a
+// multiple of 4), output Y n×k; 1 ≤ k ≤ 32.
+struct BatchMatvec {
+  const float* Xp;
+  const float* V;
+  float* Y;
+  int64_t n;
+  int k, d, kernel;
+  double f, s;
+};
+size_t prepared_points_bytes(int64_t n, int d);
+int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st);
+int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus);
+int batch_splits(int64_t n);
+int device_num_cus();
+
 // ---------------------------------------------------------------------------
 // Vector kernels (blas.hip).
 // Column-wise dot products of two n×k row-major blocks, accumulated in FP64

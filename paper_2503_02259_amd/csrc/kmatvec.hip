@@ -12,7 +12,7 @@ int launch_kmatvec_bf16(const Problem& p, int k, const void* V, MatvecOut out, h
 
 namespace {
 
-int num_cus() {
+int num_cus_impl() {
   static int cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
@@ -26,7 +26,11 @@ int num_cus() {
   return cached[dev];
 }
 
+int num_cus() { return num_cus_impl(); }
+
 }  // namespace
+
+int device_num_cus() { return num_cus_impl(); }
 
 int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                    int prec_override) {

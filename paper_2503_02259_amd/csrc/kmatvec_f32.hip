@@ -37,6 +37,7 @@
 #include <cstdlib>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "kvalue.h"
 
@@ -89,15 +90,16 @@ struct Args {
   int k;
 };
 
+// One work unit: row tile `rt` × J chunk `split` of one MatVec, partial sums
+// written to part[split].  Called by every thread of a 256-thread workgroup.
 template <int KERN, int D, int NB, int NV, int RB, bool GRAD, bool EXACT>
-__global__ __launch_bounds__(256) void kmv_f32(Args a) {
+__device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int split, float* smem) {
   constexpr int P = D <= 4 ? 4 : 8;
   constexpr int BM = 32 * RB * kWaves;
   constexpr int NBa = NB > 0 ? NB : 1;
   constexpr int NVa = NV > 0 ? NV : 1;
   constexpr int G2 = GRAD ? 2 : 1;  // contractions: k·v and (GRAD) k_l·v
   constexpr int KMAX = NB * 32 + NV;  // largest k served; EXACT: k == KMAX
-  extern __shared__ __attribute__((aligned(16))) float smem[];
   const int k = EXACT ? KMAX : a.k;   // V row stride in LDS (compile-time when EXACT)
   const int vtile = kBJ * k;
   float* Xs = smem;                 // [2][kBJ][P]
@@ -109,8 +111,6 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
   const int half = lane >> 5;
   const int l32 = lane & 31;
 
-  const int split = blockIdx.x % a.nsplit;
-  const int64_t rt = blockIdx.x / a.nsplit;
   const int jt_beg = split * a.jt_chunk;
   const int jt_end = jt_beg + a.jt_chunk < a.jt_count ? jt_beg + a.jt_chunk : a.jt_count;
 
@@ -287,6 +287,64 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
   flush();
 }
 
+template <int KERN, int D, int NB, int NV, int RB, bool GRAD, bool EXACT>
+__global__ __launch_bounds__(256) void kmv_f32(Args a) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  kmv_f32_unit<KERN, D, NB, NV, RB, GRAD, EXACT>(a, blockIdx.x / a.nsplit, blockIdx.x % a.nsplit,
+                                                  smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched MatVec of many independent problems (continuous-batching serving):
+// one persistent launch; each workgroup repeatedly takes the next work unit
+// (problem, row tile, J chunk) from a global counter.  A problem's split count
+// depends only on its own n, so its partial sums — and its result — are the
+// same whatever else is in the batch.
+
+struct BatchJob {
+  Args a;
+  int64_t first_unit;  // units of earlier jobs (prefix sum)
+  int kernel;          // HIGP_GAUSSIAN / HIGP_MATERN32
+  int dcode;           // 2, 3, 4 or 8 (padded point dimension)
+};
+
+template <int KERN>
+__device__ __forceinline__ void batch_unit(const Args& a, int dcode, int64_t rt, int split,
+                                           float* smem) {
+  if (dcode == 2) kmv_f32_unit<KERN, 2, 1, 0, 2, false, false>(a, rt, split, smem);
+  else if (dcode == 3) kmv_f32_unit<KERN, 3, 1, 0, 2, false, false>(a, rt, split, smem);
+  else if (dcode == 4) kmv_f32_unit<KERN, 4, 1, 0, 2, false, false>(a, rt, split, smem);
+  else kmv_f32_unit<KERN, 8, 1, 0, 2, false, false>(a, rt, split, smem);
+}
+
+__global__ __launch_bounds__(256) void kmv_f32_batch(const BatchJob* __restrict__ jobs, int njobs,
+                                                     int64_t total, unsigned long long* counter) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  __shared__ long long unit_sh;
+  for (;;) {
+    if (threadIdx.x == 0) unit_sh = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t u = unit_sh;
+    __syncthreads();
+    if (u >= total) break;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (jobs[mid].first_unit <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const Args a = jobs[lo].a;
+    const int64_t local = u - jobs[lo].first_unit;
+    const int64_t rt = local / a.nsplit;
+    const int split = (int)(local % a.nsplit);
+    if (jobs[lo].kernel == HIGP_GAUSSIAN)
+      batch_unit<HIGP_GAUSSIAN>(a, jobs[lo].dcode, rt, split, smem);
+    else
+      batch_unit<HIGP_MATERN32>(a, jobs[lo].dcode, rt, split, smem);
+    __syncthreads();
+  }
+}
+
 // out = f²·Σ_s P1[s] + s·V (chunks added in order, in FP64), and the
 // derivative outputs.
 __global__ void kmv_f32_epilogue(const float* __restrict__ P1, const float* __restrict__ P2,
@@ -450,6 +508,111 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) rc = set_error(HIGP_ERR_HIP, "FP32 MatVec launch failed: %s", hipGetErrorString(e));
   scratch_free(scratch, st);
+  return rc;
+}
+
+}  // namespace higp
+
+namespace higp {
+
+// Split count of one problem in a batched launch: a function of n only, so a
+// problem's partial sums do not depend on the rest of the batch.
+int batch_splits(int64_t n) {
+  const int64_t jt = (n + kBJ - 1) / kBJ;
+  int S = 1;
+  while (S < 16 && jt >= 8LL * S) S *= 2;
+  return S;
+}
+
+size_t prepared_points_bytes(int64_t n, int d) {
+  const int64_t npad = (n + kBJ - 1) / kBJ * kBJ;
+  return (size_t)npad * (d <= 4 ? 4 : 8) * 4;
+}
+
+int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st) {
+  const int P = p.d <= 4 ? 4 : 8;
+  const int64_t npad = (p.n + kBJ - 1) / kBJ * kBJ;
+  const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
+  const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
+  if (P == 4)
+    hipLaunchKernelGGL(prep_points_f32<4>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                       static_cast<const float*>(p.X), xs, Xp);
+  else
+    hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                       static_cast<const float*>(p.X), xs, Xp);
+  return hipGetLastError() == hipSuccess ? HIGP_OK : set_error(HIGP_ERR_HIP, "prep launch failed");
+}
+
+int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus) {
+  if (count <= 0) return HIGP_OK;
+  std::vector<BatchJob> hj(count);
+  size_t part_elems = 0;
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    const BatchMatvec& J = jobs[i];
+    if (J.k < 1 || J.k > 32)
+      return set_error(HIGP_ERR_UNSUPPORTED, "batched MatVec supports 1 <= k <= 32");
+    const int S = batch_splits(J.n);
+    const int64_t jt = (J.n + kBJ - 1) / kBJ;
+    const int64_t rt = (J.n + 255) / 256;  // BM = 256 (two row blocks per wave)
+    BatchJob& b = hj[i];
+    b.a = Args{};
+    b.a.Xp = J.Xp;
+    b.a.V = J.V;
+    b.a.n = J.n;
+    b.a.nk_pad = (J.n * J.k + 3) / 4 * 4;
+    b.a.jt_count = (int)jt;
+    b.a.jt_chunk = (int)((jt + S - 1) / S);
+    b.a.nsplit = S;
+    b.a.k = J.k;
+    b.first_unit = total;
+    b.kernel = J.kernel;
+    b.dcode = J.d <= 2 ? 2 : (J.d == 3 ? 3 : (J.d == 4 ? 4 : 8));
+    total += rt * S;
+    part_elems += (size_t)S * J.n * J.k;
+  }
+  const size_t jobs_bytes = ((size_t)count * sizeof(BatchJob) + 255) / 256 * 256;
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, jobs_bytes + 256 + part_elems * 4, st));
+  char* base = static_cast<char*>(mem);
+  BatchJob* djobs = reinterpret_cast<BatchJob*>(base);
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(base + jobs_bytes);
+  float* part = reinterpret_cast<float*>(base + jobs_bytes + 256);
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    hj[i].a.part = part + off;
+    off += (size_t)hj[i].a.nsplit * jobs[i].n * jobs[i].k;
+  }
+  int rc = HIGP_OK;
+  if (hipMemcpyAsync(djobs, hj.data(), count * sizeof(BatchJob), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
+    rc = set_error(HIGP_ERR_HIP, "batch setup failed");
+  const size_t lds = (size_t)2 * kBJ * (8 + 32) * 4;
+  static int bpc = 0;
+  if (bpc == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kmv_f32_batch),
+                                                     256, lds) != hipSuccess || nb < 1)
+      nb = 1;
+    bpc = nb;
+  }
+  if (rc == HIGP_OK) {
+    const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
+    hipLaunchKernelGGL(kmv_f32_batch, dim3((unsigned)grid), dim3(256), lds, st,
+                       (const BatchJob*)djobs, count, total, counter);
+    for (int i = 0; i < count && rc == HIGP_OK; ++i) {
+      const int64_t nk = jobs[i].n * jobs[i].k;
+      const unsigned eb = (unsigned)std::min<int64_t>((nk + 255) / 256, 2LL * num_cus);
+      hipLaunchKernelGGL(kmv_f32_epilogue, dim3(eb), dim3(256), 0, st, (const float*)hj[i].a.part,
+                         (const float*)nullptr, jobs[i].V, jobs[i].Y, (float*)nullptr,
+                         (float*)nullptr, nk, hj[i].a.nsplit, jobs[i].f * jobs[i].f, jobs[i].s,
+                         0.0, 0.0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = set_error(HIGP_ERR_HIP, "batched MatVec launch failed: %s", hipGetErrorString(e));
+  }
+  scratch_free(mem, st);
   return rc;
 }
 

@@ -1,0 +1,189 @@
+// PCG kernels shared by the single-call solver (higp_pcg) and the serving
+// engine.  CG scalars are FP64 on the device; x and r are FP64 vectors; the
+// search direction p is stored in the MatVec precision.  Column c stops when
+// its recursive ‖r_c‖₂ ≤ tol·‖b_c‖₂ (checked after every iteration) or after
+// max_iter iterations, and is frozen from then on.
+#pragma once
+
+#include "reduce.h"
+
+namespace higp {
+namespace {
+
+struct PcgState {
+  double* x;       // n×k FP64
+  double* r;       // n×k FP64
+  double* rho;     // k
+  double* pq;      // k
+  double* beta;    // k
+  double* bnorm;   // k
+  double* relres;  // k
+  int* active;     // k
+  int* iters;      // k
+  int* nactive;    // 1
+  double* work;    // reduction partials
+  unsigned* counter;
+  volatile int* nactive_host;  // optional pinned host copy of *nactive
+};
+
+struct PcgScalars {
+  double tol;
+  double minv;
+  int max_iter;
+};
+
+// Finalisation shared by the update and replacement kernels: from ‖r_c‖²
+// compute relres, count the iteration, freeze converged or capped columns,
+// and form ρ' = rᵀM⁻¹r and β = ρ'/ρ.
+__device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScalars& P, int c,
+                                               double rr, bool count_iter) {
+  if (!S.active[c]) {
+    S.beta[c] = 0.0;
+    return;
+  }
+  const int it = S.iters[c] + (count_iter ? 1 : 0);
+  S.iters[c] = it;
+  const double rel = S.bnorm[c] > 0.0 ? sqrt(rr) / S.bnorm[c] : 0.0;
+  S.relres[c] = rel;
+  const double rho_new = P.minv * rr;
+  S.beta[c] = rho_new / S.rho[c];
+  S.rho[c] = rho_new;
+  if (rel <= P.tol || it >= P.max_iter) S.active[c] = 0;
+}
+
+__device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
+  if (threadIdx.x == 0) {
+    int na = 0;
+    for (int c = 0; c < k; ++c) na += S.active[c];
+    *S.nactive = na;
+    if (S.nactive_host) *S.nactive_host = na;  // pinned host mirror (may be null)
+  }
+}
+
+// x += αp, r −= αq for active columns (α = ρ/pᵀq), then ‖r‖² and finish.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int64_t chunk,
+                                                          const T* __restrict__ p,
+                                                          const T* __restrict__ q, PcgState S,
+                                                          PcgScalars P, int finish) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k && S.active[c]) {
+    const double alpha = S.rho[c] / S.pq[c];
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      S.x[o] += alpha * (double)p[o];
+      const double rn = S.r[o] - alpha * (double)q[o];
+      S.r[o] = rn;
+      acc += rn * rn;
+    }
+  }
+  if (!finish) return;
+  const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
+    pcg_finish_col(S, P, col, tot, true);
+  });
+  if (last) pcg_count_active(S, k);
+}
+
+// r = b − q (true residual) for active columns, then ‖r‖² and finish.
+template <typename T, typename TQ>
+__global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int64_t chunk,
+                                                           const T* __restrict__ b,
+                                                           const TQ* __restrict__ q, PcgState S,
+                                                           PcgScalars P) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k && S.active[c]) {
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      const double rn = (double)b[o] - (double)q[o];
+      S.r[o] = rn;
+      acc += rn * rn;
+    }
+  }
+  const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
+    pcg_finish_col(S, P, col, tot, true);
+  });
+  if (last) pcg_count_active(S, k);
+}
+
+// p = M⁻¹r + βp for active columns (p in the MatVec precision).
+template <typename T>
+__global__ void pcg_pupdate(int64_t n, int k, T* __restrict__ p, PcgState S, double minv) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % k);
+    if (S.active[c]) p[e] = (T)(minv * S.r[e] + S.beta[c] * (double)p[e]);
+  }
+}
+
+// Start: x = x0 or 0; r = b − K̂x0 or b; ‖b‖, ‖r‖; p = M⁻¹r.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_start_norms(int64_t n, int k, int64_t chunk,
+                                                               const T* __restrict__ b,
+                                                               const T* __restrict__ x0,
+                                                               const T* __restrict__ q0,
+                                                               PcgState S, double* bb_out,
+                                                               double* work2,
+                                                               unsigned* counter2) {
+  __shared__ double sh[kRedThreads];
+  const int c = threadIdx.x & 63;
+  const int r0 = threadIdx.x >> 6;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  if (c < k) {
+    for (int64_t i = beg + r0; i < end; i += 4) {
+      const int64_t o = i * k + c;
+      const double bv = (double)b[o];
+      S.x[o] = x0 ? (double)x0[o] : 0.0;
+      S.r[o] = q0 ? bv - (double)q0[o] : bv;
+      acc += bv * bv;
+    }
+  }
+  (void)block_colsum_finish(acc, k, work2, counter2, sh,
+                            [&](int col, double tot) { bb_out[col] = tot; });
+}
+
+__global__ void pcg_start_finish(int k, PcgState S, PcgScalars P, const double* bb,
+                                 const double* rr) {
+  const int c = threadIdx.x;
+  if (c < k) {
+    const double bn = sqrt(bb[c]);
+    S.bnorm[c] = bn;
+    const double rel = bn > 0.0 ? sqrt(rr[c]) / bn : 0.0;
+    S.relres[c] = rel;
+    S.rho[c] = P.minv * rr[c];
+    S.iters[c] = 0;
+    S.beta[c] = 0.0;
+    S.active[c] = (rel > P.tol && P.max_iter > 0) ? 1 : 0;
+  }
+  __syncthreads();
+  pcg_count_active(S, k);
+}
+
+template <typename T>
+__global__ void pcg_pinit(int64_t n, int k, T* __restrict__ p, const double* __restrict__ r,
+                          double minv) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = (T)(minv * r[e]);
+}
+
+inline unsigned elem_blocks(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+}  // namespace
+}  // namespace higp

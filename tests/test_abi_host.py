@@ -167,3 +167,15 @@ def test_coldot_and_nlml_reject_bad_arguments():
         rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), N, ctypes.c_void_p(64),
                          ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
         assert rc == _lib.HIGP_ERR_INVALID_ARG
+
+
+def test_request_footprint_host_logic():
+    L = _lib.lib()
+    f = lambda n, d, N, m: int(L.higp_request_footprint(n, d, N, m))
+    assert f(0, 3, 16, 40) == 0 and f(100, 9, 16, 40) == 0 and f(100, 3, 32, 40) == 0
+    a, b = f(10_000, 3, 16, 40), f(20_000, 3, 16, 40)
+    assert 0 < a < b
+    # the Lanczos basis dominates: (m + 1)·n·N·8 bytes
+    assert b >= 41 * 20_000 * 16 * 8
+    assert f(10_000, 3, 16, 40) < f(10_000, 3, 16, 80)
+    assert f(10_000, 3, 0, 40) < a

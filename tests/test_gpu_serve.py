@@ -1,0 +1,101 @@
+"""Continuous-batching server (higp_server_*): results against the oracle,
+bitwise equality of a request alone and in a mix, and admission by HBM
+footprint."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2503_02259_amd import _lib, workloads as W
+from paper_2503_02259_amd.serve import Server, footprint
+from helpers import as_prec, dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _req(n, d, seed, nprobe=16):
+    X = as_prec(W.rng(2000 + seed, 0).random((n, d)), torch.float32)
+    y = as_prec(np.sin(2 * np.pi * X[:, 0]) + 0.1 * W.rng(2000 + seed, 1).standard_normal(n),
+                torch.float32)
+    Z = W.rademacher(n, nprobe, 2000 + seed) if nprobe else None
+    return X, y, Z
+
+
+def _upload(X, y, Z):
+    return (to_dev(X, torch.float32), to_dev(y, torch.float32),
+            to_dev(Z, torch.float32) if Z is not None else None)
+
+
+def _run(server, reqs, l=0.2):
+    ids = [server.submit(*_upload(*r), l=l, tol=1e-6, max_iter=1000, nsteps=30) for r in reqs]
+    for _ in range(100000):
+        na, nq = server.step()
+        if na == 0 and nq == 0:
+            break
+    out = []
+    for rid in ids:
+        x, st = server.result(rid)
+        assert st.state == _lib.HIGP_REQ_DONE
+        out.append((x.cpu().numpy().copy(), st.logdet, st.iters, st.relres, st.converged))
+    return out
+
+
+def test_single_request_matches_oracle():
+    X, y, Z = _req(3000, 3, 1)
+    srv = Server(hbm_budget=8 << 30, max_active=8)
+    (x, logdet, iters, relres, conv), = _run(srv, [(X, y, Z)])
+    srv.close()
+    assert conv and relres <= 1e-6
+    K = oracle.khat_dense(X, 0, 0.2, 1.0, 1e-2)
+    tr = np.linalg.norm(y - K @ x.astype(np.float64)) / np.linalg.norm(y)
+    Kabs = np.abs(K) @ np.abs(x.astype(np.float64))
+    floor = 6e-8 * np.linalg.norm(Kabs) / np.linalg.norm(y)
+    assert tr <= 1e-6 + 50 * floor, (tr, floor)
+    ldo, _ = oracle.slq_logdet(lambda P: K @ P, Z, 30, mdiag=np.full(3000, 1.01))
+    assert abs(logdet - ldo) <= 1e-5 * abs(ldo), (logdet, ldo)
+
+
+def test_alone_equals_in_mix_bitwise():
+    target = _req(2500, 3, 2)
+    others = [_req(n, d, 10 + i) for i, (n, d) in enumerate([(1200, 2), (4000, 8), (900, 3),
+                                                            (3300, 2), (1800, 8)])]
+    s1 = Server(hbm_budget=8 << 30, max_active=8)
+    alone = _run(s1, [target])[0]
+    s1.close()
+    s2 = Server(hbm_budget=8 << 30, max_active=8)
+    mixed = _run(s2, others[:3] + [target] + others[3:])
+    s2.close()
+    mix = mixed[3]
+    assert np.array_equal(alone[0], mix[0])
+    assert alone[1] == mix[1] and alone[2] == mix[2] and alone[3] == mix[3]
+
+
+def test_admission_respects_budget_and_all_finish():
+    reqs = [_req(n, 3, 30 + i, nprobe=8) for i, n in enumerate([2000, 2600, 1500, 3000, 2200])]
+    fps = [footprint(r[0].shape[0], 3, 8, 30) for r in reqs]
+    budget = int(max(fps) * 2.2)          # at most two requests fit at once
+    srv = Server(hbm_budget=budget, max_active=16)
+    ids = [srv.submit(*_upload(*r), l=0.2, tol=1e-6, max_iter=1000, nsteps=30) for r in reqs]
+    max_active = 0
+    for _ in range(100000):
+        na, nq = srv.step()
+        max_active = max(max_active, na)
+        assert na <= 2
+        active_fp = sum(fps[i] for i, rid in enumerate(ids) if srv.status(rid).state == _lib.HIGP_REQ_ACTIVE)
+        assert active_fp <= budget
+        if na == 0 and nq == 0:
+            break
+    assert max_active == 2
+    for rid in ids:
+        st = srv.status(rid)
+        assert st.state == _lib.HIGP_REQ_DONE and st.converged
+    srv.close()
+
+
+def test_request_larger_than_budget_is_rejected():
+    X, y, Z = _req(5000, 3, 40)
+    srv = Server(hbm_budget=1 << 20, max_active=4)
+    with pytest.raises(_lib.HigpError) as e:
+        srv.submit(*_upload(X, y, Z), l=0.2)
+    assert e.value.code == _lib.HIGP_ERR_OOM
+    srv.close()
