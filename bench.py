@@ -6,8 +6,11 @@ FP32) with inputs resident in HBM.  The headline value is kernel evaluations
 × vectors per second, n²·k / t.  After the timed steps, the same workload is
 solved by block PCG (Jacobi) to 1e-6 and its log-determinant estimated by
 SLQ (32 probes × 50 steps); their wall times are reported beside the
-headline.  The FP64 CPU oracle is timed on a bounded row sample of the same
-MatVec on the host cores.
+headline.  Further legs (extra keys, not the headline): the plain FP64 method
+at n = 2,000; the BF16 form against the FP32 form at n = 500,000, d = 8; the
+fused derivative MatVec at n = 200,000; the continuous-batching server on the
+Poisson request stream (p50/p99 latency, solves/s).  The FP64 CPU oracle is
+timed on a bounded row sample of the MatVec on the host cores.
 
 Prints one JSON line.
 """
@@ -80,6 +83,10 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the PCG/SLQ wall-time legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the CPU oracle sample (0 = all)")
+    ap.add_argument("--legs", default="fp64,bf16,grad,serve",
+                    help="comma list of extra legs (fp64, bf16, grad, serve) or 'none'")
+    ap.add_argument("--serve", type=int, default=64, metavar="N",
+                    help="requests of the serving stream to replay (the full stream has 512)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (a known-size "
                          "reference for hardware byte counters)")
@@ -166,9 +173,144 @@ def main():
         out["slq_logdet"] = ld
         out["slq_stderr"] = float(per.std(ddof=1) / np.sqrt(per.size))
 
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
+    if "fp64" in legs:
+        out["fp64_small"] = leg_fp64()
+    if "bf16" in legs:
+        out["bf16_precision_form"] = leg_bf16()
+    if "grad" in legs:
+        out["grad_matvec"] = leg_grad()
+    if "serve" in legs and args.serve > 0:
+        out["serving"] = leg_serve(args.serve)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
+
+
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def leg_fp64():
+    """Plain method, FP64: n = 2,000 uniform in [0,1]^3, Gaussian f=1, l=0.5,
+    s=0.01; one MatVec, CG to 1e-8, SLQ 10 probes × 30 steps (wall times)."""
+    import torch
+    import paper_2503_02259_amd as hg
+    from paper_2503_02259_amd import workloads as W
+    p = W.workload_fp64_small()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(p.X).to(d)
+    v = torch.from_numpy(p.extra["v"]).to(d)
+    y = torch.from_numpy(p.extra["y"]).to(d)
+    Z = torch.from_numpy(p.extra["Z"]).to(d)
+    ms = _timed(lambda: hg.kmatvec(X, v, p.kernel, p.l, p.f, p.s), 20)
+    t0 = time.perf_counter()
+    x, info = hg.pcg(X, y, p.kernel, p.l, p.f, p.s, tol=1e-8, max_iter=5000, precond="none")
+    t_cg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ld, per = hg.slq_logdet(X, Z, p.kernel, p.l, p.f, p.s, 30)
+    t_slq = time.perf_counter() - t0
+    _log("fp64 leg done")
+    return dict(workload="n=2000 d=3 Gaussian f=1 l=0.5 s=0.01, FP64", matvec_ms=ms,
+                cg_time_to_1em8_s=t_cg, cg_iters=int(info["iters"]),
+                slq_10x30_time_s=t_slq, slq_logdet=ld, pipeline_s=ms * 1e-3 + t_cg + t_slq)
+
+
+def leg_bf16():
+    """Precision form: n = 500,000 points in d = 8 from a 16-component
+    Gaussian mixture, Gaussian l = 0.3, s = 1e-3, k = 33: MatVec time of the
+    BF16 form against the FP32 form; then the literal BF16 PCG with the
+    residual recomputed in FP32 every 10 iterations on the seeded 20,000-point
+    subsample, against plain FP32 PCG (time, iterations, tracked residual)."""
+    import torch
+    import paper_2503_02259_amd as hg
+    from paper_2503_02259_amd import workloads as W
+    prob = W.workload_bf16_mixture()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(d, torch.float32)
+    V = torch.from_numpy(prob.extra["V"]).to(d, torch.float32)
+    n, k = X.shape[0], V.shape[1]
+    res = dict(workload="n=500000 d=8 16-Gaussian mixture, Gaussian l=0.3 s=1e-3, k=33")
+    for prec in ("bf16", "fp32"):
+        ms = _timed(lambda: hg.kmatvec(X, V, 0, prob.l, prob.f, prob.s, precision=prec), 3)
+        res[prec + "_matvec_ms"] = ms
+        res[prec + "_kev_vec_per_s"] = float(n) * n * k / (ms * 1e-3)
+    res["bf16_matvec_speedup"] = res["fp32_matvec_ms"] / res["bf16_matvec_ms"]
+    idx = torch.from_numpy(prob.extra["sub"]).to(d)
+    Xs, Vs = X[idx].contiguous(), V[idx].contiguous()
+    for name, kw in (("fp32_pcg", dict()),
+                     ("bf16_pcg_refine_fp32", dict(precision="bf16", refine_every=10,
+                                                   refine_prec="fp32"))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = hg.pcg(Xs, Vs, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=3000, **kw)
+        torch.cuda.synchronize()
+        res[name] = dict(time_s=time.perf_counter() - t0, iters_max=int(info["iters"].max()),
+                         converged=int(info["converged"].sum()), columns=k,
+                         relres_max=float(info["relres"].max()))
+    _log("bf16 leg done")
+    return res
+
+
+def leg_grad():
+    """Derivative MatVec: n = 200,000 uniform in [0,1]^3, Gaussian (f, l, s) =
+    (1.0, 0.2, 0.05), k = 33, FP32: K̂V, ∂K̂/∂l·V, ∂K̂/∂f·V from one fused pass."""
+    import torch
+    import paper_2503_02259_amd as hg
+    from paper_2503_02259_amd import workloads as W
+    p = W.workload_grad()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(p.X).to(d, torch.float32)
+    V = torch.from_numpy(np.concatenate([p.extra["y"][:, None], p.extra["Z"]], 1)).to(d, torch.float32)
+    n, k = X.shape[0], V.shape[1]
+    ms = _timed(lambda: hg.kmatvec_grad(X, V, 0, p.l, p.f, p.s, want=("kv", "dl", "df")), 3)
+    _log("grad leg done")
+    return dict(workload="n=200000 d=3 Gaussian f=1 l=0.2 s=0.05, k=33, FP32", ms=ms,
+                kev_vec_per_s=float(n) * n * k / (ms * 1e-3),
+                mfma_tflops=4.0 * n * n * k / (ms * 1e-3) / 1e12)
+
+
+def leg_serve(nreq):
+    """Continuous batching: the first `nreq` requests of the Poisson stream
+    (rate 200/s; n log-uniform in [1e3, 2e5]; d ∈ {2,3,8}; l ~ U[0.05,0.5];
+    s = 1e-2; FP32), each CG to 1e-6 + SLQ 16 probes × 40 steps."""
+    import torch
+    from paper_2503_02259_amd import workloads as W
+    from paper_2503_02259_amd.serve import Server, replay
+    reqs = W.serving_stream(nreq=nreq)
+    d = torch.device("cuda:0")
+
+    def upload(r):
+        return (torch.from_numpy(r.X).to(d, torch.float32), torch.from_numpy(r.y).to(d, torch.float32),
+                torch.from_numpy(r.Z).to(d, torch.float32))
+
+    stats = []
+
+    def done(i, rid, st):
+        stats.append((st.iters, st.converged, st.rounds))
+        _log("serve: %d/%d done (request %d, %d CG iterations)" % (len(stats), nreq, i, st.iters))
+
+    srv = Server(hbm_budget=128 << 30, max_active=64)
+    r = replay(reqs, srv, upload, tol=1e-6, max_iter=1000, nsteps=40, on_done=done)
+    srv.close()
+    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 + SLQ 16x40, FP32" % nreq,
+                requests=nreq, p50_s=r["p50"], p99_s=r["p99"], solves_per_s=r["throughput"],
+                span_s=r["span"], cg_iters_mean=float(np.mean([x[0] for x in stats])),
+                converged=int(sum(x[1] for x in stats)))
 
 
 if __name__ == "__main__":
