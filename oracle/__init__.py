@@ -19,7 +19,8 @@ result has no pin other than itself say "parity unpinned".
 """
 from .kernels import (GAUSSIAN, MATERN32, sqdist, kernel_value, kernel_dl,
                       khat_dense, khat_block)
-from .matvec import kmatvec, kmatvec_grad, kmatvec_bf16_emulated, round_bf16
+from .matvec import (kmatvec, kmatvec_grad, kmatvec_bf16_emulated, round_bf16,
+                     split_bf16, kmatvec_bf16x3_emulated)
 from .solvers import (pcg, lanczos, tridiag_eig, slq_logdet, slq_from_tridiag)
 from .gp import (nlml_exact, nlml_grad_exact, nlml_grad_hutchinson,
                  logdet_exact)
@@ -27,7 +28,7 @@ from .gp import (nlml_exact, nlml_grad_exact, nlml_grad_hutchinson,
 __all__ = [
     "GAUSSIAN", "MATERN32", "sqdist", "kernel_value", "kernel_dl", "khat_dense",
     "khat_block", "kmatvec", "kmatvec_grad", "kmatvec_bf16_emulated",
-    "round_bf16", "pcg", "lanczos", "tridiag_eig", "slq_logdet",
+    "round_bf16", "split_bf16", "kmatvec_bf16x3_emulated", "pcg", "lanczos", "tridiag_eig", "slq_logdet",
     "slq_from_tridiag", "nlml_exact", "nlml_grad_exact",
     "nlml_grad_hutchinson", "logdet_exact",
 ]

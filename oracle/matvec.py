@@ -101,3 +101,37 @@ def kmatvec_bf16_emulated(X, V, kernel, l, f, s, block=512, workers=1):
 
     _run_blocks(one, n, block, workers)
     return Y
+
+
+def split_bf16(a):
+    """Two-term bfloat16 split: hi = RNE(a), lo = RNE(a − hi).  With the
+    bfloat16 unit roundoff u = 2⁻⁸, |a − hi| ≤ u·|a| and
+    |a − hi − lo| ≤ u²·|a| = 2⁻¹⁶·|a|."""
+    hi = round_bf16(a)
+    return hi, round_bf16(np.asarray(a, dtype=np.float64) - hi)
+
+
+def kmatvec_bf16x3_emulated(X, V, kernel, l, f, s, block=512, workers=1):
+    """The split-BF16 form of the MatVec, emulated: the kernel tile K and V
+    are each split into hi + lo bfloat16 pairs (``split_bf16``) and the
+    product is formed from the three leading terms
+    K_hi·V_hi + K_hi·V_lo + K_lo·V_hi (the K_lo·V_lo term, of relative size
+    at most about 2⁻¹⁶, is dropped), with exact products summed in float64; then
+    Y = f²·acc + s·V with V unsplit.
+
+    Like ``kmatvec_bf16_emulated`` this predicts a kernel's arithmetic; it is
+    pinned by the split's error bound against the FP64 product, not by a value
+    the paper prints.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    n = X.shape[0]
+    Vh, Vl = split_bf16(V)
+    Y = np.empty_like(V)
+
+    def one(rows):
+        Kh, Kl = split_bf16(kernel_value(sqdist(X[rows], X), kernel, l))
+        Y[rows] = (f * f) * (Kh @ Vh + Kh @ Vl + Kl @ Vh) + s * V[rows]
+
+    _run_blocks(one, n, block, workers)
+    return Y

@@ -97,3 +97,46 @@ def test_bf16_emulated_matches_torch_rounding():
     # and the result is within bf16 accuracy of the FP64 product
     exact = oracle.kmatvec(X, V, oracle.GAUSSIAN, l, f, s)
     assert np.linalg.norm(got - exact) / np.linalg.norm(exact) < 2e-2
+
+
+def test_split_bf16_exact_for_16_bit_values_and_bounded_otherwise():
+    g = W.rng(8, 5)
+    # values with at most 16 significant bits are carried exactly by hi + lo
+    m = g.integers(2 ** 15, 2 ** 16, size=5000).astype(np.float64)
+    a = m * np.ldexp(1.0, g.integers(-40, 10, size=5000)) * g.choice([-1.0, 1.0], 5000)
+    hi, lo = oracle.split_bf16(a)
+    np.testing.assert_array_equal(hi + lo, a)
+    # general values: |a − hi − lo| ≤ 2⁻¹⁶|a|, hi and lo are bfloat16 values
+    a = g.standard_normal(20000) * np.exp(g.uniform(-20, 5, 20000))
+    hi, lo = oracle.split_bf16(a)
+    assert np.all(np.abs(a - hi - lo) <= 2.0 ** -16 * np.abs(a))
+    assert np.all(np.abs(a - hi) <= 2.0 ** -8 * np.abs(a))
+    for part in (hi, lo):
+        bf = torch.from_numpy(part).to(torch.bfloat16).double().numpy()
+        np.testing.assert_array_equal(bf, part)
+    # hi is torch's bfloat16 rounding of the (float32-representable) input
+    a32 = a.astype(np.float32).astype(np.float64)
+    hi32, _ = oracle.split_bf16(a32)
+    np.testing.assert_array_equal(hi32, torch.from_numpy(a32.astype(np.float32)).to(torch.bfloat16).double().numpy())
+
+
+@pytest.mark.parametrize("kern", [oracle.GAUSSIAN, oracle.MATERN32])
+def test_bf16x3_emulated_within_split_bound(kern):
+    """Elementwise bound of the three-term split product against the FP64
+    product: |Y − Y*| ≤ 3.1·u²·f²·(|K|·|V|), u = 2⁻⁸.  Dropping either cross
+    term, or swapping hi and lo, breaks it by a factor ~2⁸."""
+    X, V = _prob(80, 3, 4, 11)
+    l, f, s = 0.35, 1.3, 0.02
+    got = oracle.kmatvec_bf16x3_emulated(X, V, kern, l, f, s, block=32)
+    K = (RBF(l) if kern == oracle.GAUSSIAN else Matern(l, nu=1.5))(X)
+    exact = f * f * (K @ V) + s * V
+    bound = 3.1 * 2.0 ** -16 * f * f * (np.abs(K) @ np.abs(V))
+    assert np.all(np.abs(got - exact) <= bound + 1e-14)
+    # the bound is not vacuous: the single-BF16 form exceeds it
+    single = oracle.kmatvec_bf16_emulated(X, V, kern, l, f, s, block=32)
+    assert np.any(np.abs(single - exact) > 20 * bound)
+    # Rademacher vectors are exact in bfloat16 (V_lo = 0): then the result is
+    # (K_hi + K_lo)·V, within u²·|K|·|V| of the exact product
+    Z = W.rademacher(80, 3, 11)
+    gz = oracle.kmatvec_bf16x3_emulated(X, Z, kern, l, f, 0.0, block=32)
+    assert np.all(np.abs(gz - f * f * (K @ Z)) <= 1.01 * 2.0 ** -16 * f * f * (np.abs(K) @ np.abs(Z)) + 1e-14)
