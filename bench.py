@@ -231,11 +231,14 @@ def leg_fp64():
 
 
 def leg_bf16():
-    """Precision form: n = 500,000 points in d = 8 from a 16-component
-    Gaussian mixture, Gaussian l = 0.3, s = 1e-3, k = 33: MatVec time of the
-    BF16 form against the FP32 form; then the literal BF16 PCG with the
-    residual recomputed in FP32 every 10 iterations on the seeded 20,000-point
-    subsample, against plain FP32 PCG (time, iterations, tracked residual)."""
+    """Precision forms: n = 500,000 points in d = 8 from a 16-component
+    Gaussian mixture, Gaussian l = 0.3, s = 1e-3, k = 33.  MatVec time of the
+    single-BF16 and split-BF16 forms against the FP32 form; then, on the
+    seeded 20,000-point subsample, PCG to 1e-6 in the FP32 form, the literal
+    single-BF16 form with the residual recomputed in FP32 every 10
+    iterations, and the split form with FP32 and FP64 recomputes.  The true
+    relative residual of each FP64 iterate is evaluated with the library's
+    FP64 MatVec."""
     import torch
     import paper_2503_02259_amd as hg
     from paper_2503_02259_amd import workloads as W
@@ -245,23 +248,37 @@ def leg_bf16():
     V = torch.from_numpy(prob.extra["V"]).to(d, torch.float32)
     n, k = X.shape[0], V.shape[1]
     res = dict(workload="n=500000 d=8 16-Gaussian mixture, Gaussian l=0.3 s=1e-3, k=33")
-    for prec in ("bf16", "fp32"):
+    for prec in ("bf16", "bf16x3", "fp32"):
         ms = _timed(lambda: hg.kmatvec(X, V, 0, prob.l, prob.f, prob.s, precision=prec), 3)
         res[prec + "_matvec_ms"] = ms
         res[prec + "_kev_vec_per_s"] = float(n) * n * k / (ms * 1e-3)
     res["bf16_matvec_speedup"] = res["fp32_matvec_ms"] / res["bf16_matvec_ms"]
+    res["bf16x3_matvec_speedup"] = res["fp32_matvec_ms"] / res["bf16x3_matvec_ms"]
     idx = torch.from_numpy(prob.extra["sub"]).to(d)
     Xs, Vs = X[idx].contiguous(), V[idx].contiguous()
-    for name, kw in (("fp32_pcg", dict()),
-                     ("bf16_pcg_refine_fp32", dict(precision="bf16", refine_every=10,
-                                                   refine_prec="fp32"))):
+    X64 = Xs.double()
+    bn = torch.linalg.vector_norm(Vs.double(), dim=0)
+    runs = (("fp32_pcg", dict()),
+            ("bf16_pcg_refine_fp32", dict(precision="bf16", refine_every=10, refine_prec="fp32")),
+            ("bf16x3_pcg_refine_fp32", dict(precision="bf16x3", refine_every=10,
+                                            refine_prec="fp32")),
+            ("bf16x3_pcg_refine_fp64", dict(precision="bf16x3", refine_every=10,
+                                            refine_prec="fp64")))
+    for name, kw in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = hg.pcg(Xs, Vs, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=3000, **kw)
+        x, x64, info = hg.pcg(Xs, Vs, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=3000,
+                              return_fp64=True, **kw)
         torch.cuda.synchronize()
-        res[name] = dict(time_s=time.perf_counter() - t0, iters_max=int(info["iters"].max()),
+        t = time.perf_counter() - t0
+        r = Vs.double() - hg.kmatvec(X64, x64, 0, prob.l, prob.f, prob.s)
+        tr = (torch.linalg.vector_norm(r, dim=0) / bn).max().item()
+        res[name] = dict(time_s=t, iters_max=int(info["iters"].max()),
                          converged=int(info["converged"].sum()), columns=k,
-                         relres_max=float(info["relres"].max()))
+                         relres_max=float(info["relres"].max()), true_relres_max=tr)
+    base = res["fp32_pcg"]["time_s"]
+    for name in ("bf16x3_pcg_refine_fp32", "bf16x3_pcg_refine_fp64"):
+        res[name]["speedup_vs_fp32"] = base / res[name]["time_s"]
     _log("bf16 leg done")
     return res
 

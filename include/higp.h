@@ -22,9 +22,9 @@
  *    Pointers documented as "host" are ordinary host memory.
  *  - Matrices are row-major: X is n×d, and every block of vectors (V, Y, B,
  *    Xsol, Z) is n×k with element (i, c) at offset i·k + c.
- *  - Element type: double for HIGP_FP64; float for HIGP_FP32 and HIGP_BF16
- *    (in the BF16 form only the kernel tile and V are rounded to bfloat16,
- *    inside the kernel, and products are accumulated in FP32).
+ *  - Element type: double for HIGP_FP64; float for HIGP_FP32, HIGP_BF16 and
+ *    HIGP_BF16X3 (in the BF16 forms only the kernel tile and V are rounded to
+ *    bfloat16, inside the kernel, and products are accumulated in FP32).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is ordered
  *    on that stream.  higp_kmatvec and higp_kmatvec_grad only enqueue work and
  *    return; higp_pcg and higp_slq_logdet synchronise the stream before they
@@ -59,7 +59,11 @@ typedef enum { HIGP_GAUSSIAN = 0, HIGP_MATERN32 = 1 } higp_kernel;
 typedef enum {
   HIGP_FP64 = 0, /* everything in double */
   HIGP_FP32 = 1, /* distances, kernel values and the K-tile×V product in float */
-  HIGP_BF16 = 2  /* kernel tile and V rounded to bfloat16, FP32 accumulation */
+  HIGP_BF16 = 2, /* kernel tile and V rounded to bfloat16, FP32 accumulation */
+  HIGP_BF16X3 = 3 /* split BF16: kernel tile and V each as hi + lo bfloat16 pairs
+                     (hi = RNE(x), lo = RNE(x − hi)); the product keeps the three
+                     terms K_hi·V_hi + K_hi·V_lo + K_lo·V_hi, FP32 accumulation;
+                     relative error of order 2⁻¹⁶ instead of 2⁻⁸ */
 } higp_precision;
 
 /* One GP problem: K̂ = f²·k(X, X; l) + s·I.
@@ -99,7 +103,10 @@ typedef struct {
   int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂) */
   int32_t refine_every; /* R > 0: after every R-th iteration replace the recursive
                            residual by b − K̂x computed with the iterate x (FP64)
-                           and a MatVec in precision refine_prec; 0 = off */
+                           and a MatVec in precision refine_prec; a column then
+                           stops on tol only at such an iteration, so the
+                           tolerance holds for the recomputed residual (at most
+                           R − 1 extra iterations); 0 = off */
   int32_t use_x0;       /* 1: Xsol holds the initial guess on entry; 0: x0 = 0 */
   int32_t check_every;  /* host convergence poll period (≥ 1; 0 = library default).
                            Converged columns are frozen on the device, so this

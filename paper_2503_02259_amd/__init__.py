@@ -5,7 +5,7 @@ K̂ = f²·k(X, X; l) + s·I, its derivative MatVecs, and the PCG and SLQ driver
 that call it, as hand-written gfx950 HIP kernels behind a C ABI
 (``include/higp.h``).  This package is the Python binding.
 """
-from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, HigpError  # noqa: F401
+from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, BF16X3, HigpError  # noqa: F401
 
 
 def __getattr__(name):

@@ -20,6 +20,7 @@ MATERN32 = 1
 FP64 = 0
 FP32 = 1
 BF16 = 2
+BF16X3 = 3
 
 # Every symbol declared in include/higp.h.
 EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet", "higp_coldot",

@@ -3,8 +3,8 @@
 Every function only marshals arguments (shapes, dtypes, device pointers and
 the current HIP stream) and calls the library; all arithmetic of the path
 runs in the HIP kernels.  Tensors must be contiguous and on a ROCm device;
-float64 selects the FP64 form, float32 the FP32 form (or the BF16 form with
-``precision="bf16"``).
+float64 selects the FP64 form, float32 the FP32 form (or a BF16 form with
+``precision="bf16"`` or the split ``precision="bf16x3"``).
 """
 import ctypes
 
@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, HigpError  # noqa: F401
+from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, BF16X3, HigpError  # noqa: F401
 
 _KERNELS = {"gaussian": GAUSSIAN, "rbf": GAUSSIAN, "matern32": MATERN32, GAUSSIAN: GAUSSIAN,
             MATERN32: MATERN32}
@@ -32,7 +32,7 @@ def _prec(X, precision):
         if X.dtype == torch.float32:
             return FP32
         raise TypeError("X must be float64 or float32")
-    p = {"fp64": FP64, "fp32": FP32, "bf16": BF16}.get(precision, precision)
+    p = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}.get(precision, precision)
     want = torch.float64 if p == FP64 else torch.float32
     if X.dtype != want:
         raise TypeError("precision %r needs %s tensors" % (precision, want))

@@ -36,7 +36,8 @@ int validate_problem(const higp_problem* p, Problem* out) {
   if (!p) return set_error(HIGP_ERR_INVALID_ARG, "problem is NULL");
   if (p->kernel != HIGP_GAUSSIAN && p->kernel != HIGP_MATERN32)
     return set_error(HIGP_ERR_INVALID_ARG, "unknown kernel %d", p->kernel);
-  if (p->prec != HIGP_FP64 && p->prec != HIGP_FP32 && p->prec != HIGP_BF16)
+  if (p->prec != HIGP_FP64 && p->prec != HIGP_FP32 && p->prec != HIGP_BF16 &&
+      p->prec != HIGP_BF16X3)
     return set_error(HIGP_ERR_INVALID_ARG, "unknown precision %d", p->prec);
   if (p->n < 1 || p->n > (int64_t(1) << 30))
     return set_error(HIGP_ERR_INVALID_ARG, "n = %lld out of range [1, 2^30]", (long long)p->n);
@@ -217,7 +218,7 @@ int higp_coldot(int64_t n, int32_t k, int32_t prec_a, const void* A, int32_t pre
   if (k < 1 || k > HIGP_MAX_K)
     return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
   for (int pr : {prec_a, prec_b})
-    if (pr != HIGP_FP64 && pr != HIGP_FP32 && pr != HIGP_BF16)
+    if (pr != HIGP_FP64 && pr != HIGP_FP32 && pr != HIGP_BF16 && pr != HIGP_BF16X3)
       return set_error(HIGP_ERR_INVALID_ARG, "unknown precision %d", pr);
   if (!A || !B || !out) return set_error(HIGP_ERR_INVALID_ARG, "A, B and out must be non-NULL");
   return host_coldot(n, k, A, prec_a == HIGP_FP64 ? 0 : 1, B, prec_b == HIGP_FP64 ? 0 : 1, out,

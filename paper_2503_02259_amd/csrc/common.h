@@ -40,7 +40,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // Validated problem description used inside the library.
 struct Problem {
   int kernel;  // HIGP_GAUSSIAN / HIGP_MATERN32
-  int prec;    // HIGP_FP64 / HIGP_FP32 / HIGP_BF16
+  int prec;    // HIGP_FP64 / HIGP_FP32 / HIGP_BF16 / HIGP_BF16X3
   int64_t n;
   int d;
   const void* X;

@@ -8,7 +8,7 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* V, MatvecOut out, hi
 int launch_kmatvec_f64(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                        int num_cus);
 int launch_kmatvec_bf16(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
-                        int num_cus);
+                        int num_cus, bool split);
 
 namespace {
 
@@ -37,7 +37,8 @@ int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStr
   const int prec = prec_override >= 0 ? prec_override : p.prec;
   if (prec == HIGP_FP64) return launch_kmatvec_f64(p, k, V, out, st, num_cus());
   if (prec == HIGP_FP32) return launch_kmatvec_f32(p, k, V, out, st, num_cus());
-  if (prec == HIGP_BF16) return launch_kmatvec_bf16(p, k, V, out, st, num_cus());
+  if (prec == HIGP_BF16) return launch_kmatvec_bf16(p, k, V, out, st, num_cus(), false);
+  if (prec == HIGP_BF16X3) return launch_kmatvec_bf16(p, k, V, out, st, num_cus(), true);
   return set_error(HIGP_ERR_UNSUPPORTED, "precision %d is not implemented for this MatVec", prec);
 }
 

@@ -38,7 +38,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   const size_t nk = (size_t)n * k;
   const RedGrid g = red_grid(n);
   const int wp = p.prec == HIGP_FP64 ? 0 : 1;  // MatVec element type
-  const int refine_prec = p.prec == HIGP_BF16 ? HIGP_FP32 : p.prec;
+  const int refine_prec = (p.prec == HIGP_BF16 || p.prec == HIGP_BF16X3) ? HIGP_FP32 : p.prec;
   const T* B = static_cast<const T*>(Bv);
   T* Xout = static_cast<T*>(Xv);
 
@@ -94,6 +94,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   ps.tol = o.tol;
   ps.max_iter = o.max_iter;
   ps.minv = o.precond == 1 ? 1.0 / (p.f * p.f + p.s) : 1.0;
+  ps.replaced_only = o.refine_every > 0 ? 1 : 0;
 
   int rc = HIGP_OK;
   auto fail = [&](int code) {

@@ -2,7 +2,10 @@
 // engine.  CG scalars are FP64 on the device; x and r are FP64 vectors; the
 // search direction p is stored in the MatVec precision.  Column c stops when
 // its recursive ‖r_c‖₂ ≤ tol·‖b_c‖₂ (checked after every iteration) or after
-// max_iter iterations, and is frozen from then on.
+// max_iter iterations, and is frozen from then on.  With residual replacement
+// (`replaced_only`) the tolerance is tested only on a replaced residual
+// b − K̂x, so that it holds for the recomputed residual and not for a
+// recursive one that has drifted from it; the cap applies at every iteration.
 #pragma once
 
 #include "reduce.h"
@@ -30,13 +33,14 @@ struct PcgScalars {
   double tol;
   double minv;
   int max_iter;
+  int replaced_only;  // 1: stop on tol only after a residual replacement
 };
 
 // Finalisation shared by the update and replacement kernels: from ‖r_c‖²
 // compute relres, count the iteration, freeze converged or capped columns,
 // and form ρ' = rᵀM⁻¹r and β = ρ'/ρ.
 __device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScalars& P, int c,
-                                               double rr, bool count_iter) {
+                                               double rr, bool count_iter, bool replaced) {
   if (!S.active[c]) {
     S.beta[c] = 0.0;
     return;
@@ -46,9 +50,10 @@ __device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScala
   const double rel = S.bnorm[c] > 0.0 ? sqrt(rr) / S.bnorm[c] : 0.0;
   S.relres[c] = rel;
   const double rho_new = P.minv * rr;
-  S.beta[c] = rho_new / S.rho[c];
+  S.beta[c] = S.rho[c] != 0.0 ? rho_new / S.rho[c] : 0.0;
   S.rho[c] = rho_new;
-  if (rel <= P.tol || it >= P.max_iter) S.active[c] = 0;
+  const bool tol_ok = rel <= P.tol && (replaced || !P.replaced_only);
+  if (tol_ok || it >= P.max_iter) S.active[c] = 0;
 }
 
 __device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
@@ -73,7 +78,8 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < k && S.active[c]) {
-    const double alpha = S.rho[c] / S.pq[c];
+    // α = 0 once the residual is exactly zero (pᵀq = 0): x and r stay put.
+    const double alpha = S.pq[c] != 0.0 ? S.rho[c] / S.pq[c] : 0.0;
     for (int64_t i = beg + r0; i < end; i += 4) {
       const int64_t o = i * k + c;
       S.x[o] += alpha * (double)p[o];
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
   }
   if (!finish) return;
   const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
-    pcg_finish_col(S, P, col, tot, true);
+    pcg_finish_col(S, P, col, tot, true, false);
   });
   if (last) pcg_count_active(S, k);
 }
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int
     }
   }
   const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
-    pcg_finish_col(S, P, col, tot, true);
+    pcg_finish_col(S, P, col, tot, true, true);
   });
   if (last) pcg_count_active(S, k);
 }
