@@ -234,9 +234,10 @@ def leg_bf16():
     """Precision forms: n = 500,000 points in d = 8 from a 16-component
     Gaussian mixture, Gaussian l = 0.3, s = 1e-3, k = 33.  MatVec time of the
     single-BF16 and split-BF16 forms against the FP32 form; then, on the
-    seeded 20,000-point subsample, PCG to 1e-6 in the FP32 form, the literal
-    single-BF16 form with the residual recomputed in FP32 every 10
-    iterations, and the split form with FP32 and FP64 recomputes.  The true
+    seeded 20,000-point subsample, PCG to 1e-6 in the FP32 form, and the
+    literal single-BF16 and the split-BF16 forms with the residual recomputed
+    every 10 iterations in FP64 (an FP32 recompute has a floor
+    u₃₂·‖|K̂||x|‖/‖b‖ of ~1e-2 on this problem, far above the tolerance).  The true
     relative residual of each FP64 iterate is evaluated with the library's
     FP64 MatVec."""
     import torch
@@ -259,9 +260,7 @@ def leg_bf16():
     X64 = Xs.double()
     bn = torch.linalg.vector_norm(Vs.double(), dim=0)
     runs = (("fp32_pcg", dict()),
-            ("bf16_pcg_refine_fp32", dict(precision="bf16", refine_every=10, refine_prec="fp32")),
-            ("bf16x3_pcg_refine_fp32", dict(precision="bf16x3", refine_every=10,
-                                            refine_prec="fp32")),
+            ("bf16_pcg_refine_fp64", dict(precision="bf16", refine_every=10, refine_prec="fp64")),
             ("bf16x3_pcg_refine_fp64", dict(precision="bf16x3", refine_every=10,
                                             refine_prec="fp64")))
     for name, kw in runs:
@@ -277,8 +276,7 @@ def leg_bf16():
                          converged=int(info["converged"].sum()), columns=k,
                          relres_max=float(info["relres"].max()), true_relres_max=tr)
     base = res["fp32_pcg"]["time_s"]
-    for name in ("bf16x3_pcg_refine_fp32", "bf16x3_pcg_refine_fp64"):
-        res[name]["speedup_vs_fp32"] = base / res[name]["time_s"]
+    res["bf16x3_pcg_refine_fp64"]["speedup_vs_fp32"] = base / res["bf16x3_pcg_refine_fp64"]["time_s"]
     _log("bf16 leg done")
     return res
 

@@ -103,10 +103,10 @@ typedef struct {
   int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂) */
   int32_t refine_every; /* R > 0: after every R-th iteration replace the recursive
                            residual by b − K̂x computed with the iterate x (FP64)
-                           and a MatVec in precision refine_prec; a column then
-                           stops on tol only at such an iteration, so the
-                           tolerance holds for the recomputed residual (at most
-                           R − 1 extra iterations); 0 = off */
+                           and a MatVec in precision refine_prec; with
+                           HIGP_FP64 a column then stops on tol only at such an
+                           iteration, so the tolerance holds for the recomputed
+                           residual (at most R − 1 extra iterations); 0 = off */
   int32_t use_x0;       /* 1: Xsol holds the initial guess on entry; 0: x0 = 0 */
   int32_t check_every;  /* host convergence poll period (≥ 1; 0 = library default).
                            Converged columns are frozen on the device, so this
@@ -115,7 +115,12 @@ typedef struct {
                            the points widened to double; the residual is then
                            accurate to FP64, so the tolerance holds for the true
                            residual) or HIGP_FP32 (x rounded to float: cheaper,
-                           accurate only to the FP32 floor u·‖|K̂||x|‖/‖b‖) */
+                           accurate only to the FP32 floor u·‖|K̂||x|‖/‖b‖; a
+                           column takes no further replacements once one fails
+                           to lower its residual, and then converges on the
+                           recursive residual like the unrefined form).
+                           Any column whose residual becomes non-finite or
+                           exceeds 1e8·‖b‖ stops as diverged (converged = 0). */
   void* x_fp64;         /* optional (NULL = unused): device n×k double buffer that
                            receives the FP64 iterate, which is more accurate than
                            Xsol when the problem is FP32/BF16; must not overlap B

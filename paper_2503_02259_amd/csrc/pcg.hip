@@ -57,7 +57,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
                o_q = take(nk * sizeof(T)),
                o_q2 = take(refine ? nk * (refine64 ? 8 : sizeof(T)) : 0),
                o_xd = take(widen ? (size_t)n * p.d * 8 : 0),
-               o_sc = take(8 * 64 * 8), o_int = take(4 * 64 * 4),
+               o_sc = take(9 * 64 * 8), o_int = take(4 * 64 * 4),
                o_work = take(nwork * 8 * 2), o_cnt = take(2 * 4);
   void* mem = nullptr;
   HIGP_TRY(scratch_alloc(&mem, bytes, st));
@@ -79,12 +79,15 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   S.beta = sc + 128;
   S.bnorm = sc + 192;
   S.relres = sc + 256;
+  S.lastrep = sc + 448;
   double* bb = sc + 320;
   double* rr0 = sc + 384;
+  double* pr = sc + 512;  // pᵀr on the iteration after a replacement
   int* in = (int*)(base + o_int);
   S.active = in;
   S.iters = in + 64;
   S.nactive = in + 128;
+  S.norepl = in + 192;
   S.work = (double*)(base + o_work);
   double* work2 = S.work + nwork;
   S.counter = (unsigned*)(base + o_cnt);
@@ -94,7 +97,13 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   ps.tol = o.tol;
   ps.max_iter = o.max_iter;
   ps.minv = o.precond == 1 ? 1.0 / (p.f * p.f + p.s) : 1.0;
-  ps.replaced_only = o.refine_every > 0 ? 1 : 0;
+  // Stopping only on a replaced residual is sound when the replacement is
+  // accurate (FP64).  An FP32 replacement has a floor u₃₂·‖|K̂||x|‖/‖b‖ that
+  // is usually above the tolerance; a column held open by it keeps taking
+  // replacements whose noise grows with |x|, so there the recursive residual
+  // decides as without refinement.
+  ps.replaced_only = refine64 ? 1 : 0;
+  ps.stall_off = refine && !refine64 ? 1 : 0;
 
   int rc = HIGP_OK;
   auto fail = [&](int code) {
@@ -134,6 +143,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
       hipStreamSynchronize(st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "synchronisation failed"));
 
+  bool after_replace = false;
   for (int it = 1; it <= o.max_iter && nact > 0; ++it) {
     MatvecOut mo;
     mo.kv = Q;
@@ -141,9 +151,14 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
     if (rc) return fail(rc);
     rc = launch_coldot(n, k, P, wp, Q, wp, S.pq, S.work, S.counter, st);
     if (rc) return fail(rc);
+    if (after_replace) {
+      rc = launch_coldot(n, k, P, wp, S.r, 0, pr, S.work, S.counter, st);
+      if (rc) return fail(rc);
+    }
     const bool replace = o.refine_every > 0 && it % o.refine_every == 0;
     hipLaunchKernelGGL((pcg_update<T>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, k, g.chunk,
-                       (const T*)P, (const T*)Q, S, ps, replace ? 0 : 1);
+                       (const T*)P, (const T*)Q, S, ps, replace ? 0 : 1,
+                       after_replace ? (const double*)pr : nullptr);
     if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     if (replace) {
       MatvecOut m2;
@@ -165,6 +180,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
       }
       if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     }
+    after_replace = replace;
     hipLaunchKernelGGL((pcg_pupdate<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S,
                        ps.minv);
     if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));

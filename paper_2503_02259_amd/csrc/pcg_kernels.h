@@ -2,10 +2,18 @@
 // engine.  CG scalars are FP64 on the device; x and r are FP64 vectors; the
 // search direction p is stored in the MatVec precision.  Column c stops when
 // its recursive ‖r_c‖₂ ≤ tol·‖b_c‖₂ (checked after every iteration) or after
-// max_iter iterations, and is frozen from then on.  With residual replacement
-// (`replaced_only`) the tolerance is tested only on a replaced residual
-// b − K̂x, so that it holds for the recomputed residual and not for a
-// recursive one that has drifted from it; the cap applies at every iteration.
+// max_iter iterations, and is frozen from then on.  With an FP64 residual
+// replacement (`replaced_only`) the tolerance is tested only on a replaced
+// residual b − K̂x, so that it holds for the recomputed residual and not for
+// a recursive one that has drifted from it; the cap applies at every
+// iteration.  An FP32 replacement is accurate only to the floor
+// u₃₂·‖|K̂||x|‖/‖b‖; replacing at that level breaks the orthogonality CG relies
+// on (β stays near 1, p accumulates) and the iteration runs away.  So with
+// `stall_off` a column takes no further replacements once one fails to lower
+// its residual below the previous replacement's, and continues as plain
+// recursive CG (the idea of van der Vorst and Ye's residual replacement: stop
+// replacing when it no longer helps).  Any column whose residual is not
+// finite or exceeds 1e8·‖b‖ stops as diverged.
 #pragma once
 
 #include "reduce.h"
@@ -21,6 +29,8 @@ struct PcgState {
   double* beta;    // k
   double* bnorm;   // k
   double* relres;  // k
+  double* lastrep;  // k: relres after the last replacement (stall_off only)
+  int* norepl;      // k: 1 = no further replacements for this column
   int* active;     // k
   int* iters;      // k
   int* nactive;    // 1
@@ -34,6 +44,7 @@ struct PcgScalars {
   double minv;
   int max_iter;
   int replaced_only;  // 1: stop on tol only after a residual replacement
+  int stall_off;      // 1: stop replacing a column once a replacement stalls
 };
 
 // Finalisation shared by the update and replacement kernels: from ‖r_c‖²
@@ -53,7 +64,7 @@ __device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScala
   S.beta[c] = S.rho[c] != 0.0 ? rho_new / S.rho[c] : 0.0;
   S.rho[c] = rho_new;
   const bool tol_ok = rel <= P.tol && (replaced || !P.replaced_only);
-  if (tol_ok || it >= P.max_iter) S.active[c] = 0;
+  if (tol_ok || it >= P.max_iter || !(rel < 1e8)) S.active[c] = 0;
 }
 
 __device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
@@ -65,12 +76,18 @@ __device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
   }
 }
 
-// x += αp, r −= αq for active columns (α = ρ/pᵀq), then ‖r‖² and finish.
+// x += αp, r −= αq for active columns, then ‖r‖² and finish (finish = 0
+// before a replacement, which finishes instead).  α = ρ/pᵀq, or with `pr`
+// (pᵀr per column) the line-search step α = pᵀr/pᵀq.  The two agree while
+// pᵀr = ρ; a residual replacement breaks that (p was built from the old
+// residual), and one line-search step right after it restores it: the new
+// r is orthogonal to the step taken, so the next p again has pᵀr = ρ.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int64_t chunk,
                                                           const T* __restrict__ p,
                                                           const T* __restrict__ q, PcgState S,
-                                                          PcgScalars P, int finish) {
+                                                          PcgScalars P, int finish,
+                                                          const double* __restrict__ pr) {
   __shared__ double sh[kRedThreads];
   const int c = threadIdx.x & 63;
   const int r0 = threadIdx.x >> 6;
@@ -79,7 +96,8 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
   double acc = 0.0;
   if (c < k && S.active[c]) {
     // α = 0 once the residual is exactly zero (pᵀq = 0): x and r stay put.
-    const double alpha = S.pq[c] != 0.0 ? S.rho[c] / S.pq[c] : 0.0;
+    const double num = pr ? pr[c] : S.rho[c];
+    const double alpha = S.pq[c] != 0.0 ? num / S.pq[c] : 0.0;
     for (int64_t i = beg + r0; i < end; i += 4) {
       const int64_t o = i * k + c;
       S.x[o] += alpha * (double)p[o];
@@ -95,7 +113,8 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
   if (last) pcg_count_active(S, k);
 }
 
-// r = b − q (true residual) for active columns, then ‖r‖² and finish.
+// r = b − q (true residual) for active columns that still take replacements
+// (the others keep their recursive r), then ‖r‖² and finish.
 template <typename T, typename TQ>
 __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int64_t chunk,
                                                            const T* __restrict__ b,
@@ -108,15 +127,22 @@ __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < k && S.active[c]) {
+    const bool keep = S.norepl && S.norepl[c];
     for (int64_t i = beg + r0; i < end; i += 4) {
       const int64_t o = i * k + c;
-      const double rn = (double)b[o] - (double)q[o];
+      const double rn = keep ? S.r[o] : (double)b[o] - (double)q[o];
       S.r[o] = rn;
       acc += rn * rn;
     }
   }
   const bool last = block_colsum_finish(acc, k, S.work, S.counter, sh, [&](int col, double tot) {
-    pcg_finish_col(S, P, col, tot, true, true);
+    const bool repl = !(S.norepl && S.norepl[col]);
+    const bool was_active = S.active[col] != 0;
+    pcg_finish_col(S, P, col, tot, true, repl);
+    if (P.stall_off && repl && was_active) {
+      if (S.relres[col] >= S.lastrep[col]) S.norepl[col] = 1;
+      S.lastrep[col] = S.relres[col];
+    }
   });
   if (last) pcg_count_active(S, k);
 }
@@ -172,6 +198,8 @@ __global__ void pcg_start_finish(int k, PcgState S, PcgScalars P, const double* 
     S.iters[c] = 0;
     S.beta[c] = 0.0;
     S.active[c] = (rel > P.tol && P.max_iter > 0) ? 1 : 0;
+    if (S.norepl) S.norepl[c] = 0;
+    if (S.lastrep) S.lastrep[c] = __builtin_huge_val();
   }
   __syncthreads();
   pcg_count_active(S, k);

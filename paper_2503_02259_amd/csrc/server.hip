@@ -340,7 +340,8 @@ int run_round(Server& sv) {
       const RedGrid g = red_grid(n);
       HIGP_TRY(launch_coldot(n, 1, r.cg_p, 1, r.cg_q, 1, r.S.pq, r.S.work, r.S.counter, st));
       hipLaunchKernelGGL((pcg_update<float>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, 1,
-                         g.chunk, (const float*)r.cg_p, (const float*)r.cg_q, r.S, r.ps, 1);
+                         g.chunk, (const float*)r.cg_p, (const float*)r.cg_q, r.S, r.ps, 1,
+                         (const double*)nullptr);
       hipLaunchKernelGGL((pcg_pupdate<float>), dim3(elem_blocks(n)), dim3(256), 0, st, n, 1,
                          r.cg_p, r.S, r.ps.minv);
     }

@@ -91,39 +91,73 @@ def _true_residual(X, x64, B, prob):
 
 
 def test_bf16x3_pcg_refined_reaches_tolerance(mixture_sub):
-    """The split form with the residual replaced every 10 iterations reaches
-    the 1e-6 tolerance on all 33 columns.  With an FP64 replacement MatVec
-    the tolerance holds for the true residual (the solver stops on tol only
-    at a replacement); with an FP32 one, down to the FP32 floor."""
+    """The split form with the residual replaced every 10 iterations by an
+    FP64 recompute reaches 1e-6 in the true residual on all 33 columns (the
+    solver stops on tol only at a replacement).  An FP32 recompute cannot
+    here: its floor u₃₂·‖|K̂||x|‖/‖b‖, printed, is orders above 1e-6 at this
+    conditioning."""
     prob, X, V = mixture_sub
     Xd, Vd = to_dev(X, torch.float32), to_dev(V, torch.float32)
     _, info32 = hg.pcg(Xd, Vd, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=4000)
     assert info32["converged"].all()
     it32 = info32["iters"].max()
-    for rp in ("fp64", "fp32"):
-        _, x64, info = hg.pcg(Xd, Vd, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=4000,
-                              precision="bf16x3", refine_every=10, refine_prec=rp,
-                              return_fp64=True)
-        tr, floor = _true_residual(X, x64.cpu().numpy(), V, prob)
-        print("split + %s refinement: iters %d (FP32 form %d), tracked max %.2e, true max %.2e,"
-              " FP32 floor max %.2e" % (rp, info["iters"].max(), it32, info["relres"].max(),
-                                        tr.max(), floor.max()))
-        assert info["converged"].all()
-        assert info["iters"].max() <= 1.3 * it32 + 10
-        if rp == "fp64":
-            assert np.all(tr <= 1.1e-6)
-        else:
-            assert np.all(tr <= 1.1e-6 + 3 * floor)
+    _, x64, info = hg.pcg(Xd, Vd, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=4000,
+                          precision="bf16x3", refine_every=10, refine_prec="fp64",
+                          return_fp64=True)
+    tr, floor = _true_residual(X, x64.cpu().numpy(), V, prob)
+    print("split + FP64 refinement: iters %d (FP32 form %d), tracked max %.2e, true max %.2e,"
+          " FP32 floor max %.2e" % (info["iters"].max(), it32, info["relres"].max(), tr.max(),
+                                    floor.max()))
+    assert info["converged"].all()
+    assert info["iters"].max() <= 1.3 * it32 + 10
+    assert np.all(tr <= 1.1e-6)
+    assert floor.max() > 1e-3
+
+
+def test_pcg_fp32_refinement_is_stable_at_its_floor():
+    """With an FP32 recompute every 10 iterations (n = 6,000 uniform in
+    [0,1]^3, l = 0.1, s = 0.05) the true residual cannot go below the FP32
+    floor u₃₂·‖|K̂||x|‖/‖b‖ (≈1e-5 here, above the 1e-6 tolerance).  Once a
+    replacement stops lowering a column's residual the solver stops
+    replacing it, so the iteration converges in the recursive residual with
+    a finite iterate at the floor's accuracy (it used to run away).  The
+    FP64 recompute on the same problem converges in the true residual."""
+    n, l, f, s = 6000, 0.1, 1.0, 0.05
+    X = as_prec(W.uniform_points(n, 3, 94), torch.float32)
+    B = as_prec(W.gaussian_vectors(n, 5, 94), torch.float32)
+    Xd, Bd = to_dev(X, torch.float32), to_dev(B, torch.float32)
+    nb = np.linalg.norm(B, axis=0)
+    for prec in ("fp32", "bf16x3"):
+        _, x64, info = hg.pcg(Xd, Bd, 0, l, f, s, tol=1e-6, max_iter=3000, precision=prec,
+                              refine_every=10, refine_prec="fp32", return_fp64=True)
+        x64 = x64.cpu().numpy()
+        tr = np.linalg.norm(B - oracle.kmatvec(X, x64, 0, l, f, s, workers=8), axis=0) / nb
+        floor = U32 * np.linalg.norm(oracle.kmatvec(X, np.abs(x64), 0, l, f, s, workers=8),
+                                     axis=0) / nb
+        print("%s + FP32 refinement: iters %s relres %s true %s floor %s"
+              % (prec, info["iters"], info["relres"], tr, floor))
+        assert np.all(np.isfinite(x64))
+        assert info["converged"].all() and np.all(info["iters"] < 1500)
+        assert np.all(tr <= 1.1e-6 + 50 * floor)
+        _, x64, info = hg.pcg(Xd, Bd, 0, l, f, s, tol=1e-6, max_iter=3000, precision=prec,
+                              refine_every=10, refine_prec="fp64", return_fp64=True)
+        tr = np.linalg.norm(B - oracle.kmatvec(X, x64.cpu().numpy(), 0, l, f, s, workers=8),
+                            axis=0) / nb
+        print("%s + FP64 refinement: iters %s true %s" % (prec, info["iters"], tr))
+        assert info["converged"].all() and np.all(tr <= 1.1e-6)
 
 
 def test_single_bf16_pcg_on_mixture_reports_failure(mixture_sub):
     """The literal single-BF16 form on the same problem: its kernel tile is
-    indefinite at this cluster size, so refinement cannot converge; the call
-    returns normally with converged = 0 at the iteration cap."""
+    indefinite at this cluster size, so refinement (FP64 recompute, which
+    certifies the true residual) cannot converge; the call returns normally
+    with converged = 0 and a finite iterate, stopped by the cap or by the
+    divergence guard."""
     prob, X, V = mixture_sub
     Xd, Vd = to_dev(X, torch.float32), to_dev(V[:, :4].copy(), torch.float32)
     x, info = hg.pcg(Xd, Vd, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=300,
-                     precision="bf16", refine_every=10, refine_prec="fp32")
-    print("single BF16 + refinement: converged", info["converged"], "relres", info["relres"])
+                     precision="bf16", refine_every=10, refine_prec="fp64")
+    print("single BF16 + refinement: iters", info["iters"], "relres", info["relres"])
     assert not info["converged"].any()
-    assert np.all(info["iters"] == 300)
+    assert np.all(info["iters"] <= 300)
+    assert np.all(np.isfinite(x.cpu().numpy()))
