@@ -11,13 +11,14 @@ __global__ __launch_bounds__(kRedThreads) void coldot_kernel(int64_t n, int k, i
                                                              double* out, double* work,
                                                              unsigned* counter) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(k);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double s = 0.0;
   if (c < k)
-    for (int64_t i = beg + r0; i < end; i += 4) s += ld(A, i * k + c) * ld(B, i * k + c);
+    for (int64_t i = beg + r0; i < end; i += L.step) s += ld(A, i * k + c) * ld(B, i * k + c);
   (void)block_colsum_finish(s, k, work, counter, sh, [&](int col, double tot) { out[col] = tot; });
 }
 

@@ -61,13 +61,14 @@ __global__ __launch_bounds__(kRedThreads) void point_mean(int64_t n, int d, int6
                                                           float* __restrict__ ctr, double* work,
                                                           unsigned* counter) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(d);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < d)
-    for (int64_t i = beg + r0; i < end; i += 4) acc += (double)X[i * d + c];
+    for (int64_t i = beg + r0; i < end; i += L.step) acc += (double)X[i * d + c];
   (void)block_colsum_finish(acc, d, work, counter, sh,
                             [&](int col, double tot) { ctr[col] = (float)(tot / (double)n); });
 }

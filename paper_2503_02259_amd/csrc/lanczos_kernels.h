@@ -42,13 +42,14 @@ __global__ __launch_bounds__(kRedThreads) void lz_alpha(int64_t n, int N, int64_
                                                         const double* __restrict__ Qj,
                                                         LzState S) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(N);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < N)
-    for (int64_t i = beg + r0; i < end; i += 4) {
+    for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * N + c;
       const double w = isq * (double)WW[o];
       S.W[o] = w;
@@ -73,22 +74,18 @@ __global__ void lz_three_term(int64_t count, int N, const double* __restrict__ Q
 // part[t][b][c] = Σ_{i in row block b} Q_t[i][c]·W[i][c]; grid (blocks, j+1).
 __global__ __launch_bounds__(kRedThreads) void lz_coef(int64_t n, int N, int64_t chunk, LzState S) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(N);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int t = blockIdx.y;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   const double* Qt = S.Q + (int64_t)t * n * N;
   double acc = 0.0;
   if (c < N)
-    for (int64_t i = beg + r0; i < end; i += 4) acc += Qt[i * N + c] * S.W[i * N + c];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int tid = threadIdx.x;
-    S.part[((int64_t)t * gridDim.x + blockIdx.x) * 64 + tid] =
-        ((sh[tid] + sh[tid + 64]) + sh[tid + 128]) + sh[tid + 192];
-  }
+    for (int64_t i = beg + r0; i < end; i += L.step) acc += Qt[i * N + c] * S.W[i * N + c];
+  block_colsum(acc, N, sh);
+  if ((int)threadIdx.x < N) S.part[((int64_t)t * gridDim.x + blockIdx.x) * 64 + threadIdx.x] = sh[threadIdx.x];
 }
 
 // coef[t][c] = Σ_b part[t][b][c] in block order; one block per t.
@@ -105,13 +102,14 @@ __global__ void lz_coef_final(int nb, LzState S) {
 __global__ __launch_bounds__(kRedThreads) void lz_reorth_norm(int64_t n, int N, int64_t chunk,
                                                               int nt, int j, int m, LzState S) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(N);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < N)
-    for (int64_t i = beg + r0; i < end; i += 4) {
+    for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * N + c;
       double w = S.W[o];
       for (int t = 0; t < nt; ++t) w -= S.coef[t * 64 + c] * S.Q[(int64_t)t * n * N + o];

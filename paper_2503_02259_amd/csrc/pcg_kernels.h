@@ -89,8 +89,9 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
                                                           PcgScalars P, int finish,
                                                           const double* __restrict__ pr) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(k);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
     // α = 0 once the residual is exactly zero (pᵀq = 0): x and r stay put.
     const double num = pr ? pr[c] : S.rho[c];
     const double alpha = S.pq[c] != 0.0 ? num / S.pq[c] : 0.0;
-    for (int64_t i = beg + r0; i < end; i += 4) {
+    for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * k + c;
       S.x[o] += alpha * (double)p[o];
       const double rn = S.r[o] - alpha * (double)q[o];
@@ -121,14 +122,15 @@ __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int
                                                            const TQ* __restrict__ q, PcgState S,
                                                            PcgScalars P) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(k);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < k && S.active[c]) {
     const bool keep = S.norepl && S.norepl[c];
-    for (int64_t i = beg + r0; i < end; i += 4) {
+    for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * k + c;
       const double rn = keep ? S.r[o] : (double)b[o] - (double)q[o];
       S.r[o] = rn;
@@ -168,13 +170,14 @@ __global__ __launch_bounds__(kRedThreads) void pcg_start_norms(int64_t n, int k,
                                                                double* work2,
                                                                unsigned* counter2) {
   __shared__ double sh[kRedThreads];
-  const int c = threadIdx.x & 63;
-  const int r0 = threadIdx.x >> 6;
+  const ColLanes L = col_lanes(k);
+  const int c = L.c;
+  const int r0 = L.r0;
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double acc = 0.0;
   if (c < k) {
-    for (int64_t i = beg + r0; i < end; i += 4) {
+    for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * k + c;
       const double bv = (double)b[o];
       S.x[o] = x0 ? (double)x0[o] : 0.0;

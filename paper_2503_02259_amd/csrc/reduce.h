@@ -1,9 +1,12 @@
 // Deterministic column reductions over n×k row-major blocks (k ≤ 64).
 //
-// A grid of G blocks covers the rows in fixed chunks; each block writes its
-// 64 per-column partial sums, and the last block to finish (ticket counter)
-// adds the G partials in block order.  The result does not depend on
-// scheduling, so repeated runs and runs inside a batch are bitwise equal.
+// A grid of G blocks covers the rows in fixed chunks.  Inside a block the 256
+// threads form cw = 2^⌈log₂k⌉ column lanes × 256/cw row lanes (so a single
+// column still uses every thread); the row lanes are summed by a fixed tree,
+// each block writes its per-column partial sums, and the last block to finish
+// (ticket counter) adds the G partials in block order.  The result depends
+// only on n and k, not on scheduling, so repeated runs and runs inside a
+// batch are bitwise equal.
 #pragma once
 
 #include "common.h"
@@ -29,22 +32,46 @@ inline RedGrid red_grid(int64_t n) {
   return RedGrid{(int)g, chunk};
 }
 
-// Block-level: reduce `v` (this thread's partial for column tid&63) over the
-// 4 row lanes; writes work[blockIdx.x*64 + c].  Then the last block sums all
-// partials in order and calls fin(c, total) for c < k (threads 0..k-1).
-// Must be called by all threads of the block.  `sh` is 256 doubles of LDS.
-// Returns true (in every thread) only in the block that ran fin; the caller
-// must not use __syncthreads() afterwards in the other blocks.
+// Thread → (column lane c, first row r0, row stride) for k ≤ 64 columns.
+struct ColLanes {
+  int c, r0, step, lg;
+};
+
+__device__ __forceinline__ ColLanes col_lanes(int k) {
+  const int lg = k <= 1 ? 0 : 32 - __clz(k - 1);  // cw = 2^lg ≥ k
+  ColLanes L;
+  L.lg = lg;
+  L.c = (int)threadIdx.x & ((1 << lg) - 1);
+  L.r0 = (int)threadIdx.x >> lg;
+  L.step = kRedThreads >> lg;
+  return L;
+}
+
+// Block-level: sum `v` (this thread's partial for its column lane) over the
+// row lanes by a fixed tree; on return sh[c] (c < cw) holds column c's block
+// sum.  Must be called by all threads.  `sh` is 256 doubles of LDS.
+__device__ __forceinline__ void block_colsum(double v, int k, double* sh) {
+  const ColLanes L = col_lanes(k);
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = L.step >> 1; s > 0; s >>= 1) {
+    if (L.r0 < s) sh[tid] += sh[tid + (s << L.lg)];
+    __syncthreads();
+  }
+}
+
+// Block sums as above, written to work[blockIdx.x*64 + c]; then the last
+// block sums all partials in a fixed order and calls fin(c, total) for c < k
+// (threads 0..k-1).  Must be called by all threads of the block.  Returns
+// true (in every thread) only in the block that ran fin; the caller must not
+// use __syncthreads() afterwards in the other blocks.
 template <typename Fin>
 __device__ __forceinline__ bool block_colsum_finish(double v, int k, double* work,
                                                     unsigned* counter, double* sh, Fin fin) {
   const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  if (tid < 64) {
-    const double s = ((sh[tid] + sh[tid + 64]) + sh[tid + 128]) + sh[tid + 192];
-    work[(int64_t)blockIdx.x * 64 + tid] = s;
-  }
+  block_colsum(v, k, sh);
+  if (tid < k) work[(int64_t)blockIdx.x * 64 + tid] = sh[tid];
   __threadfence();
   __syncthreads();
   __shared__ unsigned ticket;
@@ -52,13 +79,16 @@ __device__ __forceinline__ bool block_colsum_finish(double v, int k, double* wor
   __syncthreads();
   if (ticket != gridDim.x - 1) return false;
   __threadfence();
-  if (tid < k) {
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
-      s += __hip_atomic_load(&work[(int64_t)b * 64 + tid], __ATOMIC_RELAXED,
+  // Row lane r of column c adds the partials of blocks r, r + step, … in
+  // order; the lanes are then combined by the fixed tree.
+  const ColLanes L = col_lanes(k);
+  double s = 0.0;
+  if (L.c < k)
+    for (unsigned b = L.r0; b < gridDim.x; b += L.step)
+      s += __hip_atomic_load(&work[(int64_t)b * 64 + L.c], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
-    fin(tid, s);
-  }
+  block_colsum(s, k, sh);
+  if (tid < k) fin(tid, sh[tid]);
   if (tid == 0) *counter = 0u;
   __syncthreads();
   return true;
