@@ -309,21 +309,34 @@ struct BatchJob {
 };
 
 // Column kinds of a batched launch: 0 = k ≤ 32 through one 32-column MFMA
-// block; 1 / 2 = k = 1 / 2 on the VALU only (a CG-only round).
+// block; 1 / 2 = k = 1 / 2 on the VALU only (a CG-only round).  The VALU
+// kinds take four 32-row blocks per wave (more independent work per LDS read
+// of a point) and reserve LDS only for the columns they carry, so more
+// workgroups fit on a CU.
 template <int KIND> struct KindCols;
-template <> struct KindCols<0> { static constexpr int NB = 1, NV = 0; };
-template <> struct KindCols<1> { static constexpr int NB = 0, NV = 1; };
-template <> struct KindCols<2> { static constexpr int NB = 0, NV = 2; };
+template <> struct KindCols<0> { static constexpr int NB = 1, NV = 0, RB = 2, KMAX = 32; };
+template <> struct KindCols<1> { static constexpr int NB = 0, NV = 1, RB = 4, KMAX = 1; };
+template <> struct KindCols<2> { static constexpr int NB = 0, NV = 2, RB = 4, KMAX = 2; };
+
+template <int KIND>
+constexpr int64_t kind_rows() {  // rows per work unit
+  return 32LL * KindCols<KIND>::RB * kWaves;
+}
+
+template <int KIND>
+constexpr size_t kind_lds() {  // X tile (8 floats a point) + V tile, double-buffered
+  return (size_t)2 * kBJ * (8 + KindCols<KIND>::KMAX) * 4;
+}
 
 template <int KERN, int KIND>
 __device__ __forceinline__ void batch_unit(const Args& a, int dcode, int64_t rt, int split,
                                            float* smem) {
-  constexpr int NB = KindCols<KIND>::NB, NV = KindCols<KIND>::NV;
+  constexpr int NB = KindCols<KIND>::NB, NV = KindCols<KIND>::NV, RB = KindCols<KIND>::RB;
   constexpr bool EX = KIND != 0;  // k = 1 and k = 2 are exact
-  if (dcode == 2) kmv_f32_unit<KERN, 2, NB, NV, 2, false, EX>(a, rt, split, smem);
-  else if (dcode == 3) kmv_f32_unit<KERN, 3, NB, NV, 2, false, EX>(a, rt, split, smem);
-  else if (dcode == 4) kmv_f32_unit<KERN, 4, NB, NV, 2, false, EX>(a, rt, split, smem);
-  else kmv_f32_unit<KERN, 8, NB, NV, 2, false, EX>(a, rt, split, smem);
+  if (dcode == 2) kmv_f32_unit<KERN, 2, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else if (dcode == 3) kmv_f32_unit<KERN, 3, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else if (dcode == 4) kmv_f32_unit<KERN, 4, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else kmv_f32_unit<KERN, 8, NB, NV, RB, false, EX>(a, rt, split, smem);
 }
 
 template <int KIND>
@@ -578,7 +591,7 @@ int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const B
           hipSuccess ||
       hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
     rc = set_error(HIGP_ERR_HIP, "batch setup failed");
-  const size_t lds = (size_t)2 * kBJ * (8 + 32) * 4;
+  const size_t lds = kind_lds<KIND>();
   static int bpc = 0;
   if (bpc == 0) {
     int nb = 0;
@@ -623,7 +636,8 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
     const int kind = J.k == 1 ? 1 : (J.k == 2 ? 2 : 0);
     const int S = batch_splits(J.n);
     const int64_t jt = (J.n + kBJ - 1) / kBJ;
-    const int64_t rt = (J.n + 255) / 256;  // BM = 256 (two row blocks per wave)
+    const int64_t bm = kind == 0 ? kind_rows<0>() : kind_rows<1>();
+    const int64_t rt = (J.n + bm - 1) / bm;
     BatchJob b{};
     b.a.Xp = J.Xp;
     b.a.V = J.V;

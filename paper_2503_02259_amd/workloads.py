@@ -132,18 +132,24 @@ class Request:
     Z: np.ndarray
 
 
+STREAM_LEN = 512
+
+
 def serving_stream(nreq=512, rate=200.0, nmin=1000, nmax=200_000,
                    dims=(2, 3, 8), nprobe=16, workload=5, materialise=True):
     """Independent GP solves arriving as a Poisson stream: exponential
     inter-arrival times at ``rate`` per second; n = ⌊exp U[ln nmin, ln nmax]⌋;
     d uniform over ``dims``; X uniform in [0,1]^d; l ~ U[0.05, 0.5]; f=1,
-    s=1e-2 (Gaussian kernel); y as above and ``nprobe`` Rademacher probes."""
+    s=1e-2 (Gaussian kernel); y as above and ``nprobe`` Rademacher probes.
+    The stream is drawn for 512 requests (or ``nreq`` if larger) and the first
+    ``nreq`` are returned, so a shorter replay is a prefix of the full one."""
     g = rng(workload, 6)
-    gaps = g.exponential(1.0 / rate, size=nreq)
+    m = max(nreq, STREAM_LEN)
+    gaps = g.exponential(1.0 / rate, size=m)[:nreq]
     arrivals = np.cumsum(gaps) - gaps[0]
-    ns = np.floor(np.exp(g.uniform(math.log(nmin), math.log(nmax), size=nreq))).astype(np.int64)
-    ds = g.choice(np.asarray(dims), size=nreq)
-    ls = g.uniform(0.05, 0.5, size=nreq)
+    ns = np.floor(np.exp(g.uniform(math.log(nmin), math.log(nmax), size=m))).astype(np.int64)[:nreq]
+    ds = g.choice(np.asarray(dims), size=m)[:nreq]
+    ls = g.uniform(0.05, 0.5, size=m)[:nreq]
     out = []
     for i in range(nreq):
         if materialise:
