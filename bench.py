@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_MFMA_FP32 = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
 PROFILE = os.path.join(ROOT, "profiles", "kmv_f32_gauss_n100000_k33.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2503_02259_amd", "csrc", "kmatvec_f32.hip")
+# Sources of the FP32 MatVec kernel the counters were taken on.
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2503_02259_amd", "csrc", f)
+               for f in ("kmv_f32_tile.h", "kmatvec_f32.hip")]
 
 
 def measured_traffic():
@@ -37,7 +39,7 @@ def measured_traffic():
     import hashlib
     try:
         txt = open(PROFILE).read()
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRCS)).hexdigest()[:16]
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in txt.splitlines()

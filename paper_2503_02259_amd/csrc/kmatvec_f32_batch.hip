@@ -1,0 +1,211 @@
+// Batched FP32 on-the-fly MatVec of many independent problems (continuous-
+// batching serving), built on the tile unit of the single-problem MatVec.
+#include <algorithm>
+#include <vector>
+
+#include "kmv_f32_tile.h"
+
+namespace higp {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched MatVec of many independent problems (continuous-batching serving):
+// one persistent launch; each workgroup repeatedly takes the next work unit
+// (problem, row tile, J chunk) from a global counter.  A problem's split count
+// depends only on its own n, so its partial sums — and its result — are the
+// same whatever else is in the batch.
+
+struct BatchJob {
+  Args a;
+  int64_t first_unit;  // units of earlier jobs of the same launch (prefix sum)
+  int kernel;          // HIGP_GAUSSIAN / HIGP_MATERN32
+  int dcode;           // 2, 3, 4 or 8 (padded point dimension)
+};
+
+// Column kinds of a batched launch: 0 = k ≤ 32 through one 32-column MFMA
+// block; 1 / 2 = k = 1 / 2 on the VALU only (a CG-only round).  The VALU
+// kinds take four 32-row blocks per wave (more independent work per LDS read
+// of a point) and reserve LDS only for the columns they carry, so more
+// workgroups fit on a CU.
+template <int KIND> struct KindCols;
+template <> struct KindCols<0> { static constexpr int NB = 1, NV = 0, RB = 2, KMAX = 32; };
+template <> struct KindCols<1> { static constexpr int NB = 0, NV = 1, RB = 4, KMAX = 1; };
+template <> struct KindCols<2> { static constexpr int NB = 0, NV = 2, RB = 4, KMAX = 2; };
+
+template <int KIND>
+constexpr int64_t kind_rows() {  // rows per work unit
+  return 32LL * KindCols<KIND>::RB * kWaves;
+}
+
+template <int KIND>
+constexpr size_t kind_lds() {  // X tile (8 floats a point) + V tile, double-buffered
+  return (size_t)2 * kBJ * (8 + KindCols<KIND>::KMAX) * 4;
+}
+
+template <int KERN, int KIND>
+__device__ __forceinline__ void batch_unit(const Args& a, int dcode, int64_t rt, int split,
+                                           float* smem) {
+  constexpr int NB = KindCols<KIND>::NB, NV = KindCols<KIND>::NV, RB = KindCols<KIND>::RB;
+  constexpr bool EX = KIND != 0;  // k = 1 and k = 2 are exact
+  if (dcode == 2) kmv_f32_unit<KERN, 2, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else if (dcode == 3) kmv_f32_unit<KERN, 3, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else if (dcode == 4) kmv_f32_unit<KERN, 4, NB, NV, RB, false, EX>(a, rt, split, smem);
+  else kmv_f32_unit<KERN, 8, NB, NV, RB, false, EX>(a, rt, split, smem);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void kmv_f32_batch(const BatchJob* __restrict__ jobs, int njobs,
+                                                     int64_t total, unsigned long long* counter) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  __shared__ long long unit_sh;
+  for (;;) {
+    if (threadIdx.x == 0) unit_sh = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t u = unit_sh;
+    __syncthreads();
+    if (u >= total) break;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (jobs[mid].first_unit <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const Args a = jobs[lo].a;
+    const int64_t local = u - jobs[lo].first_unit;
+    const int64_t rt = local / a.nsplit;
+    const int split = (int)(local % a.nsplit);
+    if (jobs[lo].kernel == HIGP_GAUSSIAN)
+      batch_unit<HIGP_GAUSSIAN, KIND>(a, jobs[lo].dcode, rt, split, smem);
+    else
+      batch_unit<HIGP_MATERN32, KIND>(a, jobs[lo].dcode, rt, split, smem);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+
+// Split count of one problem in a batched launch: a function of n only, so a
+// problem's partial sums do not depend on the rest of the batch.
+int batch_splits(int64_t n) {
+  const int64_t jt = (n + kBJ - 1) / kBJ;
+  int S = 1;
+  while (S < 16 && jt >= 8LL * S) S *= 2;
+  return S;
+}
+
+size_t prepared_points_bytes(int64_t n, int d) {
+  const int64_t npad = (n + kBJ - 1) / kBJ * kBJ;
+  return (size_t)npad * (d <= 4 ? 4 : 8) * 4;
+}
+
+int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st) {
+  const int P = p.d <= 4 ? 4 : 8;
+  const int64_t npad = (p.n + kBJ - 1) / kBJ * kBJ;
+  const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
+  const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
+  if (P == 4)
+    hipLaunchKernelGGL(prep_points_f32<4>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                       static_cast<const float*>(p.X), xs, Xp);
+  else
+    hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
+                       static_cast<const float*>(p.X), xs, Xp);
+  return hipGetLastError() == hipSuccess ? HIGP_OK : set_error(HIGP_ERR_HIP, "prep launch failed");
+}
+
+namespace {
+
+template <int KIND>
+int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const BatchMatvec*>& src,
+                      int64_t total, size_t part_elems, hipStream_t st, int num_cus) {
+  const int count = (int)hj.size();
+  if (count == 0) return HIGP_OK;
+  const size_t jobs_bytes = ((size_t)count * sizeof(BatchJob) + 255) / 256 * 256;
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, jobs_bytes + 256 + part_elems * 4, st));
+  char* base = static_cast<char*>(mem);
+  BatchJob* djobs = reinterpret_cast<BatchJob*>(base);
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(base + jobs_bytes);
+  float* part = reinterpret_cast<float*>(base + jobs_bytes + 256);
+  std::vector<BatchJob> j2 = hj;
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    j2[i].a.part = part + off;
+    off += (size_t)j2[i].a.nsplit * src[i]->n * src[i]->k;
+  }
+  int rc = HIGP_OK;
+  if (hipMemcpyAsync(djobs, j2.data(), count * sizeof(BatchJob), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
+    rc = set_error(HIGP_ERR_HIP, "batch setup failed");
+  const size_t lds = kind_lds<KIND>();
+  static int bpc = 0;
+  if (bpc == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(kmv_f32_batch<KIND>), 256, lds) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    bpc = nb;
+  }
+  if (rc == HIGP_OK) {
+    const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
+    hipLaunchKernelGGL(kmv_f32_batch<KIND>, dim3((unsigned)grid), dim3(256), lds, st,
+                       (const BatchJob*)djobs, count, total, counter);
+    for (int i = 0; i < count; ++i) {
+      const int64_t nk = src[i]->n * src[i]->k;
+      const unsigned eb = (unsigned)std::min<int64_t>((nk + 255) / 256, 2LL * num_cus);
+      hipLaunchKernelGGL(kmv_f32_epilogue, dim3(eb), dim3(256), 0, st, (const float*)j2[i].a.part,
+                         (const float*)nullptr, src[i]->V, src[i]->Y, (float*)nullptr,
+                         (float*)nullptr, nk, j2[i].a.nsplit, src[i]->f * src[i]->f, src[i]->s,
+                         0.0, 0.0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      rc = set_error(HIGP_ERR_HIP, "batched MatVec launch failed: %s", hipGetErrorString(e));
+  }
+  scratch_free(mem, st);
+  return rc;
+}
+
+}  // namespace
+
+int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus) {
+  if (count <= 0) return HIGP_OK;
+  std::vector<BatchJob> hj[3];
+  std::vector<const BatchMatvec*> src[3];
+  int64_t total[3] = {0, 0, 0};
+  size_t part_elems[3] = {0, 0, 0};
+  for (int i = 0; i < count; ++i) {
+    const BatchMatvec& J = jobs[i];
+    if (J.k < 1 || J.k > 32)
+      return set_error(HIGP_ERR_UNSUPPORTED, "batched MatVec supports 1 <= k <= 32");
+    const int kind = J.k == 1 ? 1 : (J.k == 2 ? 2 : 0);
+    const int S = batch_splits(J.n);
+    const int64_t jt = (J.n + kBJ - 1) / kBJ;
+    const int64_t bm = kind == 0 ? kind_rows<0>() : kind_rows<1>();
+    const int64_t rt = (J.n + bm - 1) / bm;
+    BatchJob b{};
+    b.a.Xp = J.Xp;
+    b.a.V = J.V;
+    b.a.n = J.n;
+    b.a.nk_pad = (J.n * J.k + 3) / 4 * 4;
+    b.a.jt_count = (int)jt;
+    b.a.jt_chunk = (int)((jt + S - 1) / S);
+    b.a.nsplit = S;
+    b.a.k = J.k;
+    b.first_unit = total[kind];
+    b.kernel = J.kernel;
+    b.dcode = J.d <= 2 ? 2 : (J.d == 3 ? 3 : (J.d == 4 ? 4 : 8));
+    total[kind] += rt * S;
+    part_elems[kind] += (size_t)S * J.n * J.k;
+    hj[kind].push_back(b);
+    src[kind].push_back(&J);
+  }
+  HIGP_TRY(launch_batch_kind<0>(hj[0], src[0], total[0], part_elems[0], st, num_cus));
+  HIGP_TRY(launch_batch_kind<1>(hj[1], src[1], total[1], part_elems[1], st, num_cus));
+  HIGP_TRY(launch_batch_kind<2>(hj[2], src[2], total[2], part_elems[2], st, num_cus));
+  return HIGP_OK;
+}
+
+}  // namespace higp
