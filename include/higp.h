@@ -96,6 +96,16 @@ int higp_kmatvec_grad(const higp_problem* p, int32_t k, const void* V,
                       void* KV, void* dL_V, void* dF_V, void* dS_V,
                       void* stream);
 
+/* Rectangular on-the-fly MatVec Y = f²·k(Xq, X; l)·V, the product prediction
+ * needs (`gpr_prediction` in Listing 1), formed block by block like K̂·V.
+ * p: the training problem — X device n×d; its s is not used; prec HIGP_FP64
+ *    or HIGP_FP32 (the BF16 forms return HIGP_ERR_UNSUPPORTED).
+ * m: number of query points (1 ≤ m ≤ 2^31); Xq: device m×d, same element
+ *    type as X.  V: device n×k; Y: device m×k, must not overlap V or Xq;
+ *    1 ≤ k ≤ HIGP_MAX_K.  Asynchronous on `stream`.                         */
+int higp_kmatvec_cross(const higp_problem* p, int64_t m, const void* Xq,
+                       int32_t k, const void* V, void* Y, void* stream);
+
 /* Options of higp_pcg.                                                     */
 typedef struct {
   double tol;           /* stop column c when ‖r_c‖₂ ≤ tol·‖b_c‖₂ (recursive r); > 0 */
@@ -216,6 +226,30 @@ int higp_nlml(const higp_problem* p, const void* y, int32_t nprobe, const void* 
  * alone and in any mix.  All work is ordered on opts.stream; higp_server_step
  * synchronises it.  A server is not thread-safe.
  * ------------------------------------------------------------------------ */
+/* Options of higp_gpr_predict.                                             */
+typedef struct {
+  double tol;        /* PCG tolerance of the solves with K̂ (> 0) */
+  int32_t max_iter;  /* PCG cap per solve (≥ 1; the paper's prediction runs use 50) */
+  int32_t precond;   /* 0 = none, 1 = Jacobi */
+  int32_t want_var;  /* 1: also the latent predictive variance; 0: mean only */
+  int32_t reserved;  /* must be 0 */
+} higp_predict_opts;
+
+/* GP regression prediction (`gpr_prediction` in Listing 1), the textbook GP
+ * posterior with the trained Θ = (l, f, s) of p:
+ *   mean_q = f²·k(x_q, X)·α,  α = K̂⁻¹y (PCG),
+ *   var_q  = f² − k*_qᵀK̂⁻¹k*_q with k*_q = f²·k(X, x_q) — the variance of the
+ *            latent function (add s for a noisy observation); a value the
+ *            solver tolerance leaves below 0 is reported as 0.
+ * p: prec HIGP_FP64 or HIGP_FP32.  y: device n; Xq: device m×d (element type
+ * of X); mean: device m; var: device m, non-NULL iff want_var (one PCG solve
+ * with up to 64 right-hand sides per 64 query points).  pcg_iters (host,
+ * nullable): iterations of the α solve.  Scratch is allocated and released
+ * inside; synchronises `stream` before returning.                          */
+int higp_gpr_predict(const higp_problem* p, const void* y, int64_t m,
+                     const void* Xq, const higp_predict_opts* opts, void* mean,
+                     void* var, int32_t* pcg_iters, void* stream);
+
 typedef struct higp_server higp_server;  /* opaque */
 
 typedef struct {

@@ -11,8 +11,8 @@ from ._lib import GAUSSIAN, MATERN32, FP64, FP32, BF16, BF16X3, HigpError  # noq
 def __getattr__(name):
     # Import the torch-facing API lazily so that `workloads` and the build
     # script can be used without importing torch.
-    if name in ("kmatvec", "kmatvec_grad", "pcg", "slq_logdet", "tridiag_eig", "problem",
-                "coldot", "nlml"):
+    if name in ("kmatvec", "kmatvec_grad", "kmatvec_cross", "pcg", "slq_logdet", "tridiag_eig",
+                "problem", "coldot", "nlml", "gpr_predict"):
         from . import api
         return getattr(api, name)
     if name in ("KMatVecFn", "GPLossFn", "GPRModel"):

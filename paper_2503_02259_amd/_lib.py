@@ -23,8 +23,8 @@ BF16 = 2
 BF16X3 = 3
 
 # Every symbol declared in include/higp.h.
-EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet", "higp_coldot",
-           "higp_nlml", "higp_request_footprint", "higp_server_create", "higp_server_submit",
+EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_pcg",
+           "higp_slq_logdet", "higp_coldot", "higp_nlml", "higp_gpr_predict", "higp_request_footprint", "higp_server_create", "higp_server_submit",
            "higp_server_step", "higp_server_status", "higp_server_destroy", "higp_tridiag_eig",
            "higp_error_string", "higp_last_error", "higp_version")
 
@@ -54,6 +54,12 @@ class NlmlOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
                 ("nsteps", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PredictOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("want_var", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -100,6 +106,9 @@ def lib():
         PP = ctypes.POINTER(Problem)
         L.higp_kmatvec.argtypes = [PP, i32, vp, vp, vp]
         L.higp_kmatvec_grad.argtypes = [PP, i32, vp, vp, vp, vp, vp, vp]
+        L.higp_kmatvec_cross.argtypes = [PP, i64, vp, i32, vp, vp, vp]
+        L.higp_gpr_predict.argtypes = [PP, vp, i64, vp, ctypes.POINTER(PredictOpts), vp, vp,
+                                       ctypes.POINTER(i32), vp]
         L.higp_pcg.argtypes = [PP, i32, vp, vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), vp]
         L.higp_slq_logdet.argtypes = [PP, i32, i32, vp, ctypes.c_uint64, i32, i32, dp, dp, vp]
         L.higp_tridiag_eig.argtypes = [i32, dp, dp, dp, dp]
@@ -118,7 +127,8 @@ def lib():
         L.higp_last_error.argtypes = []
         L.higp_last_error.restype = ctypes.c_char_p
         L.higp_version.argtypes = []
-        for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_pcg", "higp_slq_logdet",
+        for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_gpr_predict",
+                     "higp_pcg", "higp_slq_logdet",
                      "higp_coldot", "higp_nlml", "higp_tridiag_eig", "higp_version",
                      "higp_server_create", "higp_server_submit", "higp_server_step",
                      "higp_server_status", "higp_server_destroy"):

@@ -216,3 +216,46 @@ def nlml(X, y, Z, kernel, l, f, s, tol=1e-6, max_iter=2000, precond="jacobi", re
                                    ctypes.byref(logdet), ctypes.byref(its),
                                    _stream(stream, X.device)))
     return loss.value, grad, dict(logdet=logdet.value, pcg_iters=its.value)
+
+
+def kmatvec_cross(Xq, X, V, kernel, l, f, precision=None, out=None, stream=None):
+    """Y = f²·k(Xq, X; l)·V (rectangular; the product prediction needs).
+    X: n×d training points, Xq: m×d query points, V: n×k (or n)."""
+    p = problem(X, kernel, l, f, 0.0, precision)
+    V2, squeeze = _as2d(V)
+    k = V2.shape[1]
+    m = Xq.shape[0]
+    if Xq.dim() != 2 or Xq.shape[1] != p.d:
+        raise ValueError("Xq must be m×%d" % p.d)
+    xq = _dev(Xq, "Xq", X.dtype)
+    vp = _dev(V2, "V", X.dtype, (p.n, k))
+    Y = out if out is not None else torch.empty((m, k), dtype=X.dtype, device=X.device)
+    yp = _dev(Y, "Y", X.dtype, (m, k))
+    _lib.check(_lib.lib().higp_kmatvec_cross(ctypes.byref(p), m, xq, k, vp, yp,
+                                            _stream(stream, X.device)))
+    return Y[:, 0] if squeeze else Y
+
+
+def gpr_predict(X, y, Xq, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi",
+                want_var=False, precision=None, stream=None):
+    """GP regression prediction at the query points Xq with the trained
+    (l, f, s): returns (mean, var, info) — var is the latent predictive
+    variance (None unless want_var) and info holds the iterations of the
+    α = K̂⁻¹y solve."""
+    p = problem(X, kernel, l, f, s, precision)
+    m = Xq.shape[0]
+    if Xq.dim() != 2 or Xq.shape[1] != p.d:
+        raise ValueError("Xq must be m×%d" % p.d)
+    yp = _dev(y, "y", X.dtype, (p.n,))
+    xq = _dev(Xq, "Xq", X.dtype)
+    mean = torch.empty(m, dtype=X.dtype, device=X.device)
+    var = torch.empty(m, dtype=X.dtype, device=X.device) if want_var else None
+    o = _lib.PredictOpts(tol=float(tol), max_iter=int(max_iter),
+                         precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
+                         want_var=1 if want_var else 0, reserved=0)
+    its = ctypes.c_int32()
+    _lib.check(_lib.lib().higp_gpr_predict(
+        ctypes.byref(p), yp, m, xq, ctypes.byref(o), ctypes.c_void_p(mean.data_ptr()),
+        ctypes.c_void_p(var.data_ptr()) if var is not None else None, ctypes.byref(its),
+        _stream(stream, X.device)))
+    return mean, var, dict(pcg_iters=its.value)

@@ -14,6 +14,9 @@ int run_slq(const Problem& p, int N, int m, const void* Z, int reorth, int preco
             double* logdet, double* per_probe, hipStream_t st);
 int run_nlml(const Problem& p, const void* y, int N, const void* Z, const higp_nlml_opts& o,
              double* loss, double* grad, double* logdet, int32_t* iters, hipStream_t st);
+int run_predict(const Problem& p, const void* y, int64_t m, const void* Xq,
+                const higp_predict_opts& o, void* mean, void* var, int32_t* pcg_iters,
+                hipStream_t st);
 int host_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, double* out,
                 hipStream_t st);
 
@@ -242,6 +245,51 @@ int higp_nlml(const higp_problem* hp, const void* y, int32_t nprobe, const void*
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
   return run_nlml(p, y, nprobe, Z, *o, loss, grad, logdet, pcg_iters,
                   static_cast<hipStream_t>(stream));
+}
+
+int higp_kmatvec_cross(const higp_problem* hp, int64_t m, const void* Xq, int32_t k,
+                       const void* V, void* Y, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (p.prec != HIGP_FP64 && p.prec != HIGP_FP32)
+    return set_error(HIGP_ERR_UNSUPPORTED, "the rectangular MatVec runs in FP64 or FP32");
+  if (m < 1 || m > (int64_t(1) << 31))
+    return set_error(HIGP_ERR_INVALID_ARG, "m = %lld out of range", (long long)m);
+  if (k < 1 || k > HIGP_MAX_K)
+    return set_error(HIGP_ERR_INVALID_ARG, "k = %d out of range [1, %d]", k, HIGP_MAX_K);
+  if (!Xq || !V || !Y) return set_error(HIGP_ERR_INVALID_ARG, "Xq, V and Y must be non-NULL");
+  const size_t es = elem_size(p.prec);
+  const size_t ybytes = (size_t)m * k * es;
+  if (overlaps(Y, ybytes, V, (size_t)p.n * k * es) || overlaps(Y, ybytes, Xq, (size_t)m * p.d * es))
+    return set_error(HIGP_ERR_INVALID_ARG, "Y overlaps V or Xq");
+  return launch_kmatvec_cross(p, m, Xq, k, V, Y, static_cast<hipStream_t>(stream));
+}
+
+int higp_gpr_predict(const higp_problem* hp, const void* y, int64_t m, const void* Xq,
+                     const higp_predict_opts* o, void* mean, void* var, int32_t* pcg_iters,
+                     void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (p.prec != HIGP_FP64 && p.prec != HIGP_FP32)
+    return set_error(HIGP_ERR_UNSUPPORTED, "prediction runs in FP64 or FP32");
+  if (m < 1 || m > (int64_t(1) << 31))
+    return set_error(HIGP_ERR_INVALID_ARG, "m = %lld out of range", (long long)m);
+  if (!y || !Xq || !o || !mean)
+    return set_error(HIGP_ERR_INVALID_ARG, "y, Xq, opts and mean must be non-NULL");
+  if (!(o->tol > 0.0) || o->max_iter < 1 || (o->precond != 0 && o->precond != 1) ||
+      (o->want_var != 0 && o->want_var != 1) || o->reserved != 0)
+    return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
+  if ((o->want_var != 0) != (var != nullptr))
+    return set_error(HIGP_ERR_INVALID_ARG, "var must be non-NULL exactly when want_var is 1");
+  const size_t es = elem_size(p.prec);
+  const size_t mbytes = (size_t)m * es;
+  if (overlaps(mean, mbytes, y, (size_t)p.n * es) || overlaps(mean, mbytes, Xq, mbytes * p.d) ||
+      (var && (overlaps(var, mbytes, mean, mbytes) || overlaps(var, mbytes, y, (size_t)p.n * es) ||
+               overlaps(var, mbytes, Xq, mbytes * p.d))))
+    return set_error(HIGP_ERR_INVALID_ARG, "an output overlaps an input or the other output");
+  return run_predict(p, y, m, Xq, *o, mean, var, pcg_iters, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

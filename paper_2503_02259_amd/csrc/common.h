@@ -67,6 +67,10 @@ struct MatvecOut {
 };
 int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                    int prec_override = -1);
+// Rectangular Y = f²·k(Xq, X)·V: m rows (query points Xq, element type of X),
+// n = p.n J points; FP64 and FP32 only.
+int launch_kmatvec_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                         void* Y, hipStream_t st);
 
 // One problem of a batched FP32 MatVec (serving): prepared points (see
 // prepare_points_f32), V n×k (16-byte aligned, zero up to n·k rounded up to a

@@ -9,6 +9,10 @@ int launch_kmatvec_f64(const Problem& p, int k, const void* V, MatvecOut out, hi
                        int num_cus);
 int launch_kmatvec_bf16(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                         int num_cus, bool split);
+int launch_kmatvec_f32_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                             void* Y, hipStream_t st, int num_cus);
+int launch_kmatvec_f64_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                             void* Y, hipStream_t st, int num_cus);
 
 namespace {
 
@@ -40,6 +44,13 @@ int launch_kmatvec(const Problem& p, int k, const void* V, MatvecOut out, hipStr
   if (prec == HIGP_BF16) return launch_kmatvec_bf16(p, k, V, out, st, num_cus(), false);
   if (prec == HIGP_BF16X3) return launch_kmatvec_bf16(p, k, V, out, st, num_cus(), true);
   return set_error(HIGP_ERR_UNSUPPORTED, "precision %d is not implemented for this MatVec", prec);
+}
+
+int launch_kmatvec_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                         void* Y, hipStream_t st) {
+  if (p.prec == HIGP_FP64) return launch_kmatvec_f64_cross(p, m, Xq, k, V, Y, st, num_cus());
+  if (p.prec == HIGP_FP32) return launch_kmatvec_f32_cross(p, m, Xq, k, V, Y, st, num_cus());
+  return set_error(HIGP_ERR_UNSUPPORTED, "the rectangular MatVec runs in FP64 or FP32");
 }
 
 }  // namespace higp

@@ -109,9 +109,12 @@ int blocks_per_cu(Fn fn, size_t lds) {
 
 }  // namespace
 
-int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, hipStream_t st,
-                       int num_cus) {
+// Y = K̂V (Xq null; m = n) or the rectangular Y = f²·k(Xq, X)·V with m rows.
+static int run_f32(const Problem& p, int64_t m, const float* Xq, int k, const void* Vin,
+                   MatvecOut out, hipStream_t st, int num_cus) {
   const bool grad = out.dl != nullptr || out.df != nullptr;
+  const bool cross = Xq != nullptr;
+  const int64_t rows = cross ? m : p.n;
   int rb = 1;
   Fn fn;
   if (p.kernel == HIGP_GAUSSIAN)
@@ -123,10 +126,12 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
 
   const int bm = 32 * rb * kWaves;
   const int P = p.d <= 4 ? 4 : 8;
-  const int64_t nk = p.n * k;
+  const int64_t nk = p.n * k;   // V elements
+  const int64_t mk = rows * k;  // Y elements
   const int64_t jt_count = (p.n + kBJ - 1) / kBJ;
   const int64_t npad = jt_count * kBJ;
-  const int64_t rt_count = (p.n + bm - 1) / bm;
+  const int64_t mpad = cross ? (m + kBJ - 1) / kBJ * kBJ : 0;
+  const int64_t rt_count = (rows + bm - 1) / bm;
   const size_t lds = (size_t)2 * kBJ * P * 4 + (size_t)2 * kBJ * k * 4;
   if (lds > 65536 &&
       hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -144,18 +149,23 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
   const int64_t grid = rt_count * S;
   if (grid > 0x7fffffffLL) return set_error(HIGP_ERR_INVALID_ARG, "n too large");
 
-  // Scratch: prepared points (whole J tiles); a zero-padded copy of V unless
-  // V is 16-byte aligned and n·k is a multiple of 4 (tiles move 16-byte
-  // chunks); the partial slots.
+  // Scratch: prepared points (whole J tiles) and, for a rectangular MatVec,
+  // prepared row points; a zero-padded copy of V unless V is 16-byte aligned
+  // and n·k is a multiple of 4 (tiles move 16-byte chunks); the partial slots.
   const bool direct_v = (reinterpret_cast<uintptr_t>(Vin) & 15) == 0 && nk % 4 == 0;
   const int64_t nk_pad = (nk + 3) / 4 * 4;
   const size_t xp_bytes = ((size_t)npad * P * 4 + 255) / 256 * 256;
   const size_t v_bytes = direct_v ? 0 : ((size_t)nk_pad * 4 + 255) / 256 * 256;
-  const size_t part_bytes = ((size_t)S * nk * 4 + 255) / 256 * 256;
+  const size_t part_bytes = ((size_t)S * mk * 4 + 255) / 256 * 256;
+  const size_t xq_bytes = ((size_t)mpad * P * 4 + 255) / 256 * 256;
   void* scratch = nullptr;
-  HIGP_TRY(scratch_alloc(&scratch, xp_bytes + v_bytes + part_bytes * (grad ? 2 : 1), st));
+  HIGP_TRY(scratch_alloc(&scratch, xp_bytes + v_bytes + part_bytes * (grad ? 2 : 1) + xq_bytes,
+                         st));
   char* base = static_cast<char*>(scratch);
   float* Xp = reinterpret_cast<float*>(base);
+  float* Xqp = cross ? reinterpret_cast<float*>(base + xp_bytes + v_bytes +
+                                                part_bytes * (grad ? 2 : 1))
+                     : Xp;
   const float* V = static_cast<const float*>(Vin);
   int rc = HIGP_OK;
   if (!direct_v) {
@@ -173,28 +183,51 @@ int launch_kmatvec_f32(const Problem& p, int k, const void* Vin, MatvecOut out, 
     else
       hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
                          static_cast<const float*>(p.X), xs, Xp);
+    if (cross) {
+      const unsigned qb = (unsigned)std::min<int64_t>((mpad * P + 255) / 256, 4096);
+      if (P == 4)
+        hipLaunchKernelGGL(prep_points_f32<4>, dim3(qb), dim3(256), 0, st, m, mpad, p.d, Xq, xs,
+                           Xqp);
+      else
+        hipLaunchKernelGGL(prep_points_f32<8>, dim3(qb), dim3(256), 0, st, m, mpad, p.d, Xq, xs,
+                           Xqp);
+    }
   }
   Args a{};
   a.Xp = Xp;
+  a.Xq = Xqp;
   a.V = V;
   a.part = reinterpret_cast<float*>(base + xp_bytes + v_bytes);
   a.part2 = grad ? reinterpret_cast<float*>(base + xp_bytes + v_bytes + part_bytes) : nullptr;
-  a.n = p.n;
+  a.m = rows;
   a.nk_pad = direct_v ? nk : nk_pad;
   a.jt_count = (int)jt_count;
   a.jt_chunk = jt_chunk;
   a.nsplit = S;
   a.k = k;
   hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), lds, st, a);
-  const unsigned eb = (unsigned)std::min<int64_t>((nk + 255) / 256, 8LL * num_cus);
+  const unsigned eb = (unsigned)std::min<int64_t>((mk + 255) / 256, 8LL * num_cus);
   hipLaunchKernelGGL(kmv_f32_epilogue, dim3(eb), dim3(256), 0, st, (const float*)a.part,
-                     (const float*)a.part2, V, static_cast<float*>(out.kv),
-                     static_cast<float*>(out.dl), static_cast<float*>(out.df), nk, S, p.f * p.f,
-                     p.s, cl, 2.0 * p.f);
+                     (const float*)a.part2, cross ? (const float*)nullptr : V,
+                     static_cast<float*>(out.kv), static_cast<float*>(out.dl),
+                     static_cast<float*>(out.df), mk, S, p.f * p.f, cross ? 0.0 : p.s, cl,
+                     2.0 * p.f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) rc = set_error(HIGP_ERR_HIP, "FP32 MatVec launch failed: %s", hipGetErrorString(e));
   scratch_free(scratch, st);
   return rc;
+}
+
+int launch_kmatvec_f32(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
+                       int num_cus) {
+  return run_f32(p, p.n, nullptr, k, V, out, st, num_cus);
+}
+
+int launch_kmatvec_f32_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                             void* Y, hipStream_t st, int num_cus) {
+  MatvecOut out;
+  out.kv = Y;
+  return run_f32(p, m, static_cast<const float*>(Xq), k, V, out, st, num_cus);
 }
 
 }  // namespace higp

@@ -187,8 +187,9 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
     const int64_t rt = (J.n + bm - 1) / bm;
     BatchJob b{};
     b.a.Xp = J.Xp;
+    b.a.Xq = J.Xp;
     b.a.V = J.V;
-    b.a.n = J.n;
+    b.a.m = J.n;
     b.a.nk_pad = (J.n * J.k + 3) / 4 * 4;
     b.a.jt_count = (int)jt;
     b.a.jt_chunk = (int)((jt + S - 1) / S);

@@ -18,12 +18,15 @@ constexpr int kWaves = 4;
 
 template <typename T>
 struct KArgs {
-  const T* X;   // n×d row-major
+  const T* X;   // n×d row-major: the J (column) points
+  const T* Xq;  // m×d row-major: the row points (X for a square MatVec)
   const T* V;   // n×k row-major
-  T* o1;        // S==1: K̂V (or null); S>1: partial Σ k·v, S×n×k
+  const T* sV;  // V for the s·V term (null for a rectangular MatVec)
+  T* o1;        // S==1: K̂V (or null); S>1: partial Σ k·v, S×m×k
   T* o2;        // S==1: ∂K̂/∂l·V (or null); S>1: partial Σ k_l·v (GRAD only)
   T* o3;        // S==1: ∂K̂/∂f·V (or null); unused when S>1
-  int64_t n;
+  int64_t n;    // J points
+  int64_t m;    // rows
   int64_t jchunk;  // J points per split (multiple of the J tile)
   int k, d, nsplit;
   T xs;          // coordinate pre-scale
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   double xi[D];
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    xi[c] = (irow < a.n && c < d) ? a.X[irow * d + c] * a.xs : 0.0;
+    xi[c] = (irow < a.m && c < d) ? a.Xq[irow * d + c] * a.xs : 0.0;
 
   f64x4 acc[NB];
   f64x4 acc2[GRAD ? NB : 1];
@@ -152,10 +155,10 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   }
 
   const bool direct = a.nsplit == 1;
-  double* p1 = direct ? a.o1 : a.o1 + (int64_t)split * a.n * k;
+  double* p1 = direct ? a.o1 : a.o1 + (int64_t)split * a.m * k;
   double* p2 = a.o2;
   if constexpr (GRAD) {
-    if (!direct) p2 = a.o2 + (int64_t)split * a.n * k;
+    if (!direct) p2 = a.o2 + (int64_t)split * a.m * k;
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -164,11 +167,11 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = row0 + wave * 16 + q + 4 * r;
-      if (row >= a.n) continue;
+      if (row >= a.m) continue;
       const int64_t o = row * k + col;
       const double s1 = acc[b][r];
       if (direct) {
-        if (a.o1) a.o1[o] = fma(a.f2, s1, a.s * a.V[o]);
+        if (a.o1) a.o1[o] = fma(a.f2, s1, a.sV ? a.s * a.sV[o] : 0.0);
         if constexpr (GRAD) {
           if (a.o2) a.o2[o] = a.cl * acc2[b][r];
           if (a.o3) a.o3[o] = a.cf * s1;
@@ -182,8 +185,9 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue over S partials: out = f²·Σ_s P1 + s·V (and the derivative
-// outputs).  Partials are added in split order in FP64.
+// Epilogue over S partials: out = f²·Σ_s P1 + s·V (no s·V term when V is
+// null) and the derivative outputs.  Partials are added in split order in
+// FP64.
 
 template <typename T>
 __global__ __launch_bounds__(256) void kmv_epilogue(const T* __restrict__ P1,
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(256) void kmv_epilogue(const T* __restrict__ P1,
       s1 += (double)P1[sp * count + e];
       if (P2) s2 += (double)P2[sp * count + e];
     }
-    if (o1) o1[e] = (T)(f2 * s1 + s * (double)V[e]);
+    if (o1) o1[e] = (T)(f2 * s1 + (V ? s * (double)V[e] : 0.0));
     if (o2) o2[e] = (T)(cl * s2);
     if (o3) o3[e] = (T)(cf * s1);
   }
@@ -224,9 +228,10 @@ KFn<double> pick_f64_d(int d, int k) {
 }
 
 // Number of J splits S (a power of two ≤ 64) so that the grid has at least
-// `want_blocks` workgroups while each split keeps `min_tiles` J tiles.
-int choose_splits(int64_t n, int bm, int bj, int min_tiles, int64_t want_blocks) {
-  const int64_t row_tiles = (n + bm - 1) / bm;
+// `want_blocks` workgroups while each split keeps `min_tiles` J tiles
+// (n J points, `rows` output rows).
+int choose_splits(int64_t n, int64_t rows, int bm, int bj, int min_tiles, int64_t want_blocks) {
+  const int64_t row_tiles = (rows + bm - 1) / bm;
   int s = 1;
   while (s < 64 && row_tiles * s < want_blocks && n / (2LL * s) >= (int64_t)min_tiles * bj) s *= 2;
   return s;
@@ -243,33 +248,39 @@ int launch_epilogue(const T* P1, const T* P2, const T* V, MatvecOut out, int64_t
                                          : set_error(HIGP_ERR_HIP, "epilogue launch failed");
 }
 
-int run_f64(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
-            KFn<double> fn, double xs, double cl, int num_cus) {
+// Y = K̂V (Xq null) or the rectangular Y = f²·k(Xq, X)·V with m rows.
+int run_f64(const Problem& p, int64_t m, const double* Xq, int k, const void* V, MatvecOut out,
+            hipStream_t st, KFn<double> fn, double xs, double cl, int num_cus) {
   constexpr int bm = 16 * kWaves;
   const bool grad = out.dl != nullptr || out.df != nullptr;
+  const bool cross = Xq != nullptr;
+  const int64_t rows = cross ? m : p.n;
   KArgs<double> a{};
   a.X = static_cast<const double*>(p.X);
+  a.Xq = cross ? Xq : a.X;
   a.V = static_cast<const double*>(V);
+  a.sV = cross ? nullptr : a.V;
   a.n = p.n;
+  a.m = rows;
   a.k = k;
   a.d = p.d;
   a.xs = xs;
   a.f2 = p.f * p.f;
-  a.s = p.s;
+  a.s = cross ? 0.0 : p.s;
   a.cl = cl;
   a.cf = 2.0 * p.f;
-  const int S = choose_splits(p.n, bm, kBJ64, 1, 4LL * num_cus);
+  const int S = choose_splits(p.n, rows, bm, kBJ64, 1, 4LL * num_cus);
   a.nsplit = S;
   const int64_t tiles_j = (p.n + kBJ64 - 1) / kBJ64;
   a.jchunk = ((tiles_j + S - 1) / S) * kBJ64;
-  const int64_t nblocks = ((p.n + bm - 1) / bm) * S;
+  const int64_t nblocks = ((rows + bm - 1) / bm) * S;
   void* scratch = nullptr;
   if (S == 1) {
     a.o1 = static_cast<double*>(out.kv);
     a.o2 = static_cast<double*>(out.dl);
     a.o3 = static_cast<double*>(out.df);
   } else {
-    const size_t per = (size_t)p.n * k * sizeof(double) * S;
+    const size_t per = (size_t)rows * k * sizeof(double) * S;
     HIGP_TRY(scratch_alloc(&scratch, per * (grad ? 2 : 1), st));
     a.o1 = static_cast<double*>(scratch);
     a.o2 = grad ? reinterpret_cast<double*>(static_cast<char*>(scratch) + per) : nullptr;
@@ -278,8 +289,8 @@ int run_f64(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t s
   int rc = hipGetLastError() == hipSuccess ? HIGP_OK
                                            : set_error(HIGP_ERR_HIP, "FP64 MatVec launch failed");
   if (rc == HIGP_OK && S > 1)
-    rc = launch_epilogue<double>(a.o1, grad ? a.o2 : nullptr, a.V, out, p.n * k, S, p.f * p.f,
-                                 p.s, cl, 2.0 * p.f, st, num_cus);
+    rc = launch_epilogue<double>(a.o1, grad ? a.o2 : nullptr, a.sV, out, rows * k, S, p.f * p.f,
+                                 a.s, cl, 2.0 * p.f, st, num_cus);
   if (scratch) scratch_free(scratch, st);
   return rc;
 }
@@ -295,8 +306,18 @@ int launch_kmatvec_f64(const Problem& p, int k, const void* V, MatvecOut out, hi
     fn = grad ? pick_f64_d<HIGP_GAUSSIAN, true>(p.d, k) : pick_f64_d<HIGP_GAUSSIAN, false>(p.d, k);
   else
     fn = grad ? pick_f64_d<HIGP_MATERN32, true>(p.d, k) : pick_f64_d<HIGP_MATERN32, false>(p.d, k);
-  return run_f64(p, k, V, out, st, fn, coord_scale(p.kernel, HIGP_FP64, p.l),
+  return run_f64(p, p.n, nullptr, k, V, out, st, fn, coord_scale(p.kernel, HIGP_FP64, p.l),
                  p.f * p.f * dl_factor(p.kernel, HIGP_FP64, p.l), num_cus);
+}
+
+int launch_kmatvec_f64_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,
+                             void* Y, hipStream_t st, int num_cus) {
+  KFn<double> fn = p.kernel == HIGP_GAUSSIAN ? pick_f64_d<HIGP_GAUSSIAN, false>(p.d, k)
+                                             : pick_f64_d<HIGP_MATERN32, false>(p.d, k);
+  MatvecOut out;
+  out.kv = Y;
+  return run_f64(p, m, static_cast<const double*>(Xq), k, V, out, st, fn,
+                 coord_scale(p.kernel, HIGP_FP64, p.l), 0.0, num_cus);
 }
 
 }  // namespace higp

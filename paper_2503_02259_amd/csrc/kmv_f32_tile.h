@@ -44,11 +44,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
 }
 
 struct Args {
-  const float* Xp;  // npad×P prepared points
+  const float* Xp;  // npad×P prepared points of the J (column) side
+  const float* Xq;  // prepared points of the row side (Xp for a square MatVec)
   const float* V;   // n×k (16-byte aligned, readable up to nk_pad elements)
-  float* part;      // partials [S][n][k]: Σ k·v over each J chunk
+  float* part;      // partials [S][m][k]: Σ k·v over each J chunk
   float* part2;     // same layout: Σ k_l·v (GRAD)
-  int64_t n;
+  int64_t m;        // rows (query points; n for a square MatVec)
   int64_t nk_pad;
   int jt_count;     // J tiles
   int jt_chunk;     // J tiles per chunk
@@ -85,7 +86,7 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
   for (int rb = 0; rb < RB; ++rb) {
     const int64_t i = rt * BM + wave * 32 * RB + rb * 32 + l32;
 #pragma unroll
-    for (int c = 0; c < P; ++c) xi[rb][c] = i < a.n ? a.Xp[i * P + c] : 0.0f;
+    for (int c = 0; c < P; ++c) xi[rb][c] = i < a.m ? a.Xq[i * P + c] : 0.0f;
   }
 
   f32x16 acc[G2][RB][NBa];
@@ -131,10 +132,10 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
 
   // Partial sums of this chunk → part[split] (FP64 totals, rounded once).
   auto flush = [&]() {
-    const int64_t nk = a.n * k;
+    const int64_t nk = a.m * k;
     float* q1 = a.part + (int64_t)split * nk + rt * BM * k;
     float* q2 = GRAD ? a.part2 + (int64_t)split * nk + rt * BM * k : nullptr;
-    const int64_t rows_left = a.n - rt * BM;
+    const int64_t rows_left = a.m - rt * BM;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int lrow0 = wave * 32 * RB + rb * 32;
@@ -253,8 +254,8 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
   flush();
 }
 
-// out = f²·Σ_s P1[s] + s·V (chunks added in order, in FP64), and the
-// derivative outputs.
+// out = f²·Σ_s P1[s] + s·V (chunks added in order, in FP64; V null: no
+// s·V term, as for a rectangular MatVec), and the derivative outputs.
 __global__ void kmv_f32_epilogue(const float* __restrict__ P1, const float* __restrict__ P2,
                                  const float* __restrict__ V, float* o1, float* o2, float* o3,
                                  int64_t count, int nsplit, double f2, double s, double cl,
@@ -266,7 +267,7 @@ __global__ void kmv_f32_epilogue(const float* __restrict__ P1, const float* __re
       s1 += (double)P1[sp * count + e];
       if (P2) s2 += (double)P2[sp * count + e];
     }
-    if (o1) o1[e] = (float)(f2 * s1 + s * (double)V[e]);
+    if (o1) o1[e] = (float)(f2 * s1 + (V ? s * (double)V[e] : 0.0));
     if (o2) o2[e] = (float)(cl * s2);
     if (o3) o3[e] = (float)(cf * s1);
   }

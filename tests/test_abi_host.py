@@ -179,3 +179,45 @@ def test_request_footprint_host_logic():
     assert b >= 41 * 20_000 * 16 * 8
     assert f(10_000, 3, 16, 40) < f(10_000, 3, 16, 80)
     assert f(10_000, 3, 0, 40) < a
+
+
+def test_kmatvec_cross_validation():
+    L = _lib.lib()
+    a, b, c = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    p = _prob()
+    for m, k in ((0, 4), (-3, 4), (5, 0), (5, 65)):
+        assert L.higp_kmatvec_cross(ctypes.byref(p), m, a, k, b, c, None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_kmatvec_cross(ctypes.byref(p), 5, None, 4, b, c, None) == _lib.HIGP_ERR_INVALID_ARG
+    # Y overlapping V
+    assert L.higp_kmatvec_cross(ctypes.byref(p), 5, a, 4, b, ctypes.c_void_p(0x100010),
+                                None) == _lib.HIGP_ERR_INVALID_ARG
+    for prec in (_lib.BF16, _lib.BF16X3):
+        pb = _prob(prec=prec)
+        assert L.higp_kmatvec_cross(ctypes.byref(pb), 5, a, 4, b, c, None) == _lib.HIGP_ERR_UNSUPPORTED
+
+
+def test_gpr_predict_validation():
+    L = _lib.lib()
+    y, xq, mean, var = (ctypes.c_void_p(v) for v in (0x2000, 0x100000, 0x900000, 0xA00000))
+    good = dict(tol=1e-6, max_iter=50, precond=1, want_var=0, reserved=0)
+    p = _prob()
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=2), dict(want_var=2),
+                dict(reserved=1)):
+        o = _lib.PredictOpts(**dict(good, **bad))
+        rc = L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o), mean, None, None, None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG, bad
+    o = _lib.PredictOpts(**good)
+    # var given without want_var, and want_var without var
+    assert L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o), mean, var, None,
+                              None) == _lib.HIGP_ERR_INVALID_ARG
+    o1 = _lib.PredictOpts(**dict(good, want_var=1))
+    assert L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o1), mean, None, None,
+                              None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_gpr_predict(ctypes.byref(p), y, 0, xq, ctypes.byref(o), mean, None, None,
+                              None) == _lib.HIGP_ERR_INVALID_ARG
+    # mean overlapping y
+    assert L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o), ctypes.c_void_p(0x2004),
+                              None, None, None) == _lib.HIGP_ERR_INVALID_ARG
+    pb = _prob(prec=_lib.BF16)
+    assert L.higp_gpr_predict(ctypes.byref(pb), y, 5, xq, ctypes.byref(o), mean, None, None,
+                              None) == _lib.HIGP_ERR_UNSUPPORTED
