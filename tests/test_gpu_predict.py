@@ -7,7 +7,7 @@ import torch
 import oracle
 import paper_2503_02259_amd as hg
 from paper_2503_02259_amd import workloads as W
-from helpers import TOL, as_prec, colrel, to_dev
+from helpers import TOL, as_prec, colrel, colrel_cond, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -105,10 +105,14 @@ def test_prediction_full_size_sampled():
                          max_iter=400)
     mean = hg.kmatvec_cross(Xqd, Xd, alpha, 0, prob.l, prob.f).cpu().numpy()
     idx = W.rng(614, 3).choice(4096, 64, replace=False)
-    ref = oracle.kmatvec_cross(Xq[idx], X, alpha.double().cpu().numpy(), 0, prob.l, prob.f,
-                               workers=8)
-    err = np.linalg.norm(mean[idx] - ref) / np.linalg.norm(ref)
-    print("full-size rectangular MatVec, sampled rows: %.2e" % err)
+    a64 = alpha.double().cpu().numpy()
+    ref = oracle.kmatvec_cross(Xq[idx], X, a64, 0, prob.l, prob.f, workers=8)
+    refabs = oracle.kmatvec_cross(Xq[idx], X, np.abs(a64), 0, prob.l, prob.f, workers=8)
+    # α oscillates, so the product cancels (‖K*α‖ ≪ ‖|K*||α|‖): the error is
+    # measured against the magnitude of the summands.
+    err = colrel_cond(mean[idx], ref, refabs).max()
+    print("full-size rectangular MatVec, sampled rows: %.2e (cancellation %.1f)"
+          % (err, np.linalg.norm(refabs) / np.linalg.norm(ref)))
     assert err <= 1e-5
     m2, _, inf2 = hg.gpr_predict(Xd, to_dev(y, torch.float32), Xqd, 0, prob.l, prob.f, prob.s,
                                  tol=1e-4, max_iter=400)
