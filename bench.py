@@ -7,9 +7,10 @@ FP32) with inputs resident in HBM.  The headline value is kernel evaluations
 solved by block PCG (Jacobi) to 1e-6 and its log-determinant estimated by
 SLQ (32 probes × 50 steps); their wall times are reported beside the
 headline.  Further legs (extra keys, not the headline): the plain FP64 method
-at n = 2,000; the BF16 form against the FP32 form at n = 500,000, d = 8; the
-fused derivative MatVec at n = 200,000; the continuous-batching server on the
-Poisson request stream (p50/p99 latency, solves/s).  The FP64 CPU oracle is
+at n = 2,000; the BF16 forms against the FP32 form at n = 500,000, d = 8; the
+fused derivative MatVec at n = 200,000; hyper-parameter training with the
+paper's end-to-end settings at n = 100,000; the continuous-batching server on
+the Poisson request stream (p50/p99 latency, solves/s).  The FP64 CPU oracle is
 timed on a bounded row sample of the MatVec on the host cores.
 
 Prints one JSON line.
@@ -85,8 +86,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the PCG/SLQ wall-time legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the CPU oracle sample (0 = all)")
-    ap.add_argument("--legs", default="fp64,bf16,grad,serve",
-                    help="comma list of extra legs (fp64, bf16, grad, serve) or 'none'")
+    ap.add_argument("--legs", default="fp64,bf16,grad,train,serve",
+                    help="comma list of extra legs (fp64, bf16, grad, train, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
@@ -231,6 +232,8 @@ def main():
         out["bf16_precision_form"] = leg_bf16()
     if "grad" in legs:
         out["grad_matvec"] = leg_grad()
+    if "train" in legs:
+        out["train_e2e"] = leg_train()
     if "serve" in legs and args.serve > 0:
         out["serving"] = leg_serve(args.serve)
     if not args.no_cpu:
@@ -357,6 +360,32 @@ def leg_grad():
     return dict(workload="n=200000 d=3 Gaussian f=1 l=0.2 s=0.05, k=33, FP32", ms=ms,
                 kev_vec_per_s=float(n) * n * k / (ms * 1e-3),
                 mfma_tflops=4.0 * n * n * k / (ms * 1e-3) / 1e12)
+
+
+def leg_train():
+    """Hyper-parameter training with the paper's end-to-end settings (Adam,
+    50 steps, learning rate 0.01, 20 CG iterations per solve, FP32) on the
+    n = 100,000 workload (Gaussian, start Θ = (0.1, 1, 0.01)), 16 Rademacher
+    probes, 20 Lanczos steps, Jacobi, softplus parameters."""
+    import torch
+    from paper_2503_02259_amd import workloads as W
+    from paper_2503_02259_amd.autograd import GPRModel, train_gpr
+    prob = W.workload_fp32_matvec()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(d, torch.float32)
+    y = torch.from_numpy(prob.extra["y"]).to(d, torch.float32)
+    Z = torch.from_numpy(prob.extra["Z"][:, :16].copy()).to(d, torch.float32)
+    model = GPRModel(X, y, Z, kernel=0, l=prob.l, f=prob.f, s=prob.s,
+                     opts=dict(tol=1e-6, max_iter=20, nsteps=20), transform="softplus")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train_gpr(model, steps=50, lr=0.01)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    _log("train leg done")
+    return dict(workload="n=100000 d=3 Gaussian, 50 Adam steps lr 0.01, 20 CG its, 16 probes x 20 "
+                         "Lanczos steps, FP32", time_s=t, ms_per_step=1e3 * t / 50,
+                loss_first=hist[0]["loss"], loss_last=hist[-1]["loss"], theta_final=model.get_params())
 
 
 def leg_serve(nreq):

@@ -13,7 +13,8 @@ follows the paper's statement of the problem ("Gaussian Processes" section):
 * PCG for ``K̂⁻¹y`` with a preconditioner ``M ≈ K̂``;
 * eq. (1) (log-determinant split) with stochastic Lanczos quadrature;
 * eq. (2) (trace split) with the Hutchinson estimator;
-* prediction with the trained Θ (the textbook GP posterior).
+* prediction with the trained Θ (the textbook GP posterior);
+* the training loop (Adam on Θ with that gradient).
 
 Parity status of each function is stated in its docstring.  Functions whose
 result has no pin other than itself say "parity unpinned".
@@ -26,11 +27,13 @@ from .solvers import (pcg, lanczos, tridiag_eig, slq_logdet, slq_from_tridiag)
 from .gp import (nlml_exact, nlml_grad_exact, nlml_grad_hutchinson,
                  logdet_exact)
 from .predict import kmatvec_cross, gpr_predict
+from .train import Adam, softplus, softplus_inv, train_gpr
 
 __all__ = [
     "GAUSSIAN", "MATERN32", "sqdist", "kernel_value", "kernel_dl", "khat_dense",
     "khat_block", "kmatvec", "kmatvec_grad", "kmatvec_bf16_emulated",
     "round_bf16", "split_bf16", "kmatvec_bf16x3_emulated", "pcg", "lanczos", "tridiag_eig", "slq_logdet",
     "slq_from_tridiag", "nlml_exact", "nlml_grad_exact",
-    "nlml_grad_hutchinson", "logdet_exact", "kmatvec_cross", "gpr_predict",
+    "nlml_grad_hutchinson", "logdet_exact", "kmatvec_cross", "gpr_predict", "Adam",
+    "softplus", "softplus_inv", "train_gpr",
 ]

@@ -15,7 +15,7 @@ def __getattr__(name):
                 "problem", "coldot", "nlml", "gpr_predict"):
         from . import api
         return getattr(api, name)
-    if name in ("KMatVecFn", "GPLossFn", "GPRModel"):
+    if name in ("KMatVecFn", "GPLossFn", "GPRModel", "train_gpr"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

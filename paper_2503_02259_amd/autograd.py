@@ -9,7 +9,8 @@ entry point.
   (not autodiff through the solver), as in the paper ("Statement of Need",
   hand-coded gradients).
 * ``GPRModel``: Θ registered as torch parameters, ``calc_loss_grad()`` fills
-  their ``.grad`` (the shape of the paper's Listing 1).
+  their ``.grad`` (the shape of the paper's Listing 1); ``train_gpr`` runs
+  Adam on it.
 
 Parameters l, f, s are 0-dim tensors; X carries no gradient.
 """
@@ -69,22 +70,60 @@ class GPLossFn(torch.autograd.Function):
 
 class GPRModel(torch.nn.Module):
     """Θ = (l, f, s) as parameters over fixed data; ``calc_loss_grad()``
-    returns the loss estimate and fills the parameters' gradients."""
+    returns the loss estimate and fills the parameters' gradients.
 
-    def __init__(self, X, y, Z, kernel=0, l=1.0, f=1.0, s=0.1, opts=None):
+    ``transform=None`` registers Θ itself.  ``transform="softplus"`` registers
+    raw values ρ with Θ = log(1 + e^ρ), so that an optimizer cannot step a
+    parameter out of its domain (l > 0, s ≥ 0); the gradient reaches ρ through
+    torch's chain rule (∂L/∂ρ = ∂L/∂θ·σ(ρ))."""
+
+    def __init__(self, X, y, Z, kernel=0, l=1.0, f=1.0, s=0.1, opts=None, transform=None):
         super().__init__()
+        if transform not in (None, "softplus"):
+            raise ValueError("transform must be None or 'softplus'")
         self.X, self.y, self.Z, self.kernel = X, y, Z, kernel
         self.opts = dict(opts or {})
-        self.l = torch.nn.Parameter(torch.tensor(float(l), dtype=torch.float64, device=X.device))
-        self.f = torch.nn.Parameter(torch.tensor(float(f), dtype=torch.float64, device=X.device))
-        self.s = torch.nn.Parameter(torch.tensor(float(s), dtype=torch.float64, device=X.device))
+        self.transform = transform
+
+        def raw(v):
+            v = float(v)
+            if transform == "softplus":
+                v = v + float(torch.log(-torch.expm1(torch.tensor(-v, dtype=torch.float64))))
+            return torch.nn.Parameter(torch.tensor(v, dtype=torch.float64, device=X.device))
+
+        self.l, self.f, self.s = raw(l), raw(f), raw(s)
+
+    def theta(self):
+        """(l, f, s) as 0-dim tensors (differentiable in the raw parameters)."""
+        if self.transform == "softplus":
+            sp = torch.nn.functional.softplus
+            return sp(self.l), sp(self.f), sp(self.s)
+        return self.l, self.f, self.s
 
     def calc_loss_grad(self):
         for p in self.parameters():
             p.grad = None
-        loss = GPLossFn.apply(self.X, self.y, self.Z, self.l, self.f, self.s, self.kernel, self.opts)
+        l, f, s = self.theta()
+        loss = GPLossFn.apply(self.X, self.y, self.Z, l, f, s, self.kernel, self.opts)
         loss.backward()
         return float(loss)
 
     def get_params(self):
-        return dict(l=float(self.l), f=float(self.f), s=float(self.s))
+        l, f, s = self.theta()
+        return dict(l=float(l), f=float(f), s=float(s))
+
+
+def train_gpr(model, steps=50, lr=0.01):
+    """Adam on the model's parameters for `steps` steps (the paper's E2E
+    training settings: 50 steps at learning rate 0.01, Listing 1's loop).
+    Returns one record per step: the loss estimate and Θ before the step and
+    the raw parameters' gradients."""
+    opt = torch.optim.Adam(model.parameters(), lr=lr)
+    hist = []
+    for i in range(steps):
+        loss = model.calc_loss_grad()
+        rec = dict(step=i, loss=loss, **model.get_params())
+        rec["grad"] = [float(p.grad) for p in (model.l, model.f, model.s)]
+        hist.append(rec)
+        opt.step()
+    return hist
