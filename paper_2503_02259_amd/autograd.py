@@ -106,7 +106,7 @@ class GPRModel(torch.nn.Module):
         l, f, s = self.theta()
         loss = GPLossFn.apply(self.X, self.y, self.Z, l, f, s, self.kernel, self.opts)
         loss.backward()
-        return float(loss)
+        return float(loss.detach())
 
     def get_params(self):
         l, f, s = self.theta()
