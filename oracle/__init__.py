@@ -14,7 +14,8 @@ follows the paper's statement of the problem ("Gaussian Processes" section):
 * eq. (1) (log-determinant split) with stochastic Lanczos quadrature;
 * eq. (2) (trace split) with the Hutchinson estimator;
 * prediction with the trained Θ (the textbook GP posterior);
-* the training loop (Adam on Θ with that gradient).
+* the training loop (Adam on Θ with that gradient);
+* a low-rank (Nyström, farthest-point landmarks) preconditioner for PCG.
 
 Parity status of each function is stated in its docstring.  Functions whose
 result has no pin other than itself say "parity unpinned".
@@ -28,6 +29,7 @@ from .gp import (nlml_exact, nlml_grad_exact, nlml_grad_hutchinson,
                  logdet_exact)
 from .predict import kmatvec_cross, gpr_predict
 from .train import Adam, softplus, softplus_inv, train_gpr
+from .precond import fps_landmarks, nystrom_parts, nystrom_apply_inv, nystrom_dense
 
 __all__ = [
     "GAUSSIAN", "MATERN32", "sqdist", "kernel_value", "kernel_dl", "khat_dense",
@@ -35,5 +37,6 @@ __all__ = [
     "round_bf16", "split_bf16", "kmatvec_bf16x3_emulated", "pcg", "lanczos", "tridiag_eig", "slq_logdet",
     "slq_from_tridiag", "nlml_exact", "nlml_grad_exact",
     "nlml_grad_hutchinson", "logdet_exact", "kmatvec_cross", "gpr_predict", "Adam",
-    "softplus", "softplus_inv", "train_gpr",
+    "softplus", "softplus_inv", "train_gpr", "fps_landmarks", "nystrom_parts",
+    "nystrom_apply_inv", "nystrom_dense",
 ]

@@ -18,11 +18,11 @@ import scipy.linalg
 
 
 def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
-        true_matvec=None):
+        true_matvec=None, apply_minv=None):
     """Solve A X = B column by column with (Jacobi-)preconditioned CG.
 
     matvec(P) -> A·P for an n×k block.  mdiag: diagonal of M (None = no
-    preconditioner).  refine_every = R > 0 replaces the recursive residual by
+    preconditioner); apply_minv(R) -> M⁻¹R for a general SPD M instead.  refine_every = R > 0 replaces the recursive residual by
     the true residual b − A·x (computed with ``true_matvec``, default
     ``matvec``) after every R-th iteration of a column.
 
@@ -37,6 +37,8 @@ def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
     minv = None if mdiag is None else 1.0 / np.asarray(mdiag, dtype=np.float64)
 
     def prec(R):
+        if apply_minv is not None:
+            return apply_minv(R)
         return R.copy() if minv is None else minv[:, None] * R
 
     X = np.zeros((n, k)) if x0 is None else np.array(x0, dtype=np.float64).reshape(n, k)
