@@ -201,7 +201,9 @@ def main():
         runs = (("pcg", dict()),
                 ("pcg_fp32_refine_fp64", dict(refine_every=10, refine_prec="fp64")),
                 ("pcg_bf16x3_refine_fp64", dict(precision="bf16x3", refine_every=10,
-                                                refine_prec="fp64")))
+                                                refine_prec="fp64")),
+                ("pcg_nystrom1024_refine_fp64", dict(precond="nystrom", rank=1024,
+                                                     refine_every=10, refine_prec="fp64")))
         for name, kw in runs:
             r = _pcg_run(X, V, kern, prob, 5000, **kw)
             if name == "pcg":
@@ -212,6 +214,8 @@ def main():
                 out["pcg_true_relres_max"] = r["true_relres_max"]
             else:
                 out[name] = r
+        out["pcg_nystrom1024_refine_fp64"]["speedup_vs_fp32_refine_fp64"] = (
+            out["pcg_fp32_refine_fp64"]["time_s"] / out["pcg_nystrom1024_refine_fp64"]["time_s"])
         out["pcg_bf16x3_refine_fp64"]["speedup_vs_fp32_refine_fp64"] = (
             out["pcg_fp32_refine_fp64"]["time_s"] / out["pcg_bf16x3_refine_fp64"]["time_s"])
         out["bf16x3_matvec_ms"] = _timed(
@@ -267,14 +271,16 @@ def _pcg_run(X, B, kern, prob, max_iter, **kw):
     import paper_2503_02259_amd as hg
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    kw.setdefault("precond", "jacobi")
     x, x64, info = hg.pcg(X, B, kern, prob.l, prob.f, prob.s, tol=1e-6, max_iter=max_iter,
-                          precond="jacobi", return_fp64=True, **kw)
+                          return_fp64=True, **kw)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     B64 = B.double()
     r = B64 - hg.kmatvec(X.double(), x64, kern, prob.l, prob.f, prob.s)
     tr = (torch.linalg.vector_norm(r, dim=0) / torch.linalg.vector_norm(B64, dim=0)).max().item()
-    _log("pcg %s: %.2f s, %d iterations" % (kw.get("precision", "fp32"), t, int(info["iters"].max())))
+    _log("pcg %s/%s: %.2f s, %d iterations" % (kw.get("precision", "fp32"), kw["precond"], t,
+                                             int(info["iters"].max())))
     return dict(time_s=t, iters_max=int(info["iters"].max()), converged=int(info["converged"].sum()),
                 columns=int(B.shape[1]), relres_max=float(info["relres"].max()), true_relres_max=tr)
 

@@ -110,7 +110,12 @@ int higp_kmatvec_cross(const higp_problem* p, int64_t m, const void* Xq,
 typedef struct {
   double tol;           /* stop column c when ‖r_c‖₂ ≤ tol·‖b_c‖₂ (recursive r); > 0 */
   int32_t max_iter;     /* cap on iterations per column; ≥ 1 */
-  int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂) */
+  int32_t precond;      /* 0 = none, 1 = Jacobi (M = diag K̂), 2 = Nyström: the
+                           low-rank approximation the paper's AFN preconditioner
+                           is built on ("Statement of Need"), in its generic
+                           form M = s·I + f²·K_nr·K_rr⁻¹·K_rn on `rank` landmarks
+                           chosen by farthest-point sampling, applied by the
+                           Woodbury identity (needs s > 0) */
   int32_t refine_every; /* R > 0: after every R-th iteration replace the recursive
                            residual by b − K̂x computed with the iterate x (FP64)
                            and a MatVec in precision refine_prec; with
@@ -135,6 +140,10 @@ typedef struct {
                            receives the FP64 iterate, which is more accurate than
                            Xsol when the problem is FP32/BF16; must not overlap B
                            or Xsol */
+  int32_t rank;         /* Nyström landmarks (precond 2): 0 = min(n, 1024), else
+                           1 … 2048 (clamped to n); ignored otherwise.  Building
+                           costs n·rank² flops on the GPU and rank³/2 on the host;
+                           each application 4·n·rank·k flops */
 } higp_pcg_opts;
 
 /* Per-column results of higp_pcg (host arrays of length k, caller-owned). */
@@ -226,11 +235,21 @@ int higp_nlml(const higp_problem* p, const void* y, int32_t nprobe, const void* 
  * alone and in any mix.  All work is ordered on opts.stream; higp_server_step
  * synchronises it.  A server is not thread-safe.
  * ------------------------------------------------------------------------ */
+/* Landmark points of the Nyström preconditioner (precond 2 of higp_pcg):
+ * min(rank, n) indices into X chosen by farthest-point sampling — the first
+ * is 0, each next one is the point whose smallest squared distance (FP64,
+ * coordinates summed in order) to the landmarks so far is largest, lowest
+ * index on ties.  AFN, the paper's preconditioner, builds its Nyström part
+ * on such selected points ("Statement of Need").
+ * p: X device n×d (FP64 or FP32 coordinates; l, f, s unused).
+ * idx: host array of min(rank, n) int32.  1 ≤ rank ≤ 2048.  Synchronises. */
+int higp_fps_landmarks(const higp_problem* p, int32_t rank, int32_t* idx, void* stream);
+
 /* Options of higp_gpr_predict.                                             */
 typedef struct {
   double tol;        /* PCG tolerance of the solves with K̂ (> 0) */
   int32_t max_iter;  /* PCG cap per solve (≥ 1; the paper's prediction runs use 50) */
-  int32_t precond;   /* 0 = none, 1 = Jacobi */
+  int32_t precond;   /* 0 = none, 1 = Jacobi, 2 = Nyström with min(n, 1024) landmarks */
   int32_t want_var;  /* 1: also the latent predictive variance; 0: mean only */
   int32_t reserved;  /* must be 0 */
 } higp_predict_opts;

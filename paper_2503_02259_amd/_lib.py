@@ -24,7 +24,8 @@ BF16X3 = 3
 
 # Every symbol declared in include/higp.h.
 EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_pcg",
-           "higp_slq_logdet", "higp_coldot", "higp_nlml", "higp_gpr_predict", "higp_request_footprint", "higp_server_create", "higp_server_submit",
+           "higp_slq_logdet", "higp_coldot", "higp_nlml", "higp_gpr_predict",
+           "higp_fps_landmarks", "higp_request_footprint", "higp_server_create", "higp_server_submit",
            "higp_server_step", "higp_server_status", "higp_server_destroy", "higp_tridiag_eig",
            "higp_error_string", "higp_last_error", "higp_version")
 
@@ -41,7 +42,8 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("refine_prec", ctypes.c_int32), ("x_fp64", ctypes.c_void_p)]
+                ("refine_prec", ctypes.c_int32), ("x_fp64", ctypes.c_void_p),
+                ("rank", ctypes.c_int32)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -107,6 +109,7 @@ def lib():
         L.higp_kmatvec.argtypes = [PP, i32, vp, vp, vp]
         L.higp_kmatvec_grad.argtypes = [PP, i32, vp, vp, vp, vp, vp, vp]
         L.higp_kmatvec_cross.argtypes = [PP, i64, vp, i32, vp, vp, vp]
+        L.higp_fps_landmarks.argtypes = [PP, i32, ctypes.POINTER(i32), vp]
         L.higp_gpr_predict.argtypes = [PP, vp, i64, vp, ctypes.POINTER(PredictOpts), vp, vp,
                                        ctypes.POINTER(i32), vp]
         L.higp_pcg.argtypes = [PP, i32, vp, vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), vp]
@@ -128,6 +131,7 @@ def lib():
         L.higp_last_error.restype = ctypes.c_char_p
         L.higp_version.argtypes = []
         for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_gpr_predict",
+                     "higp_fps_landmarks",
                      "higp_pcg", "higp_slq_logdet",
                      "higp_coldot", "higp_nlml", "higp_tridiag_eig", "higp_version",
                      "higp_server_create", "higp_server_submit", "higp_server_step",

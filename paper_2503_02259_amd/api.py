@@ -103,14 +103,18 @@ def kmatvec_grad(X, V, kernel, l, f, s, precision=None, want=("kv", "dl", "df", 
     return tuple(outs)
 
 
+_PRECOND = {"jacobi": 1, "none": 0, "nystrom": 2, None: 0, 0: 0, 1: 1, 2: 2}
+
+
 def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine_every=0,
         x0=None, check_every=0, precision=None, refine_prec="fp64", return_fp64=False,
-        stream=None):
+        rank=0, stream=None):
     """Solve K̂·x = b for each column of B.  Returns (x, info) with info a dict
     of per-column numpy arrays: iters, relres (tracked residual), converged.
     With refine_every = R > 0 the tracked residual is replaced by b − K̂x every
     R iterations, the MatVec then running in `refine_prec` ("fp64"/"fp32").
-    With return_fp64 the FP64 iterate is returned as well: (x, x64, info)."""
+    With return_fp64 the FP64 iterate is returned as well: (x, x64, info).
+    precond: "none", "jacobi" or "nystrom" (``rank`` landmarks, 0 = default)."""
     p = problem(X, kernel, l, f, s, precision)
     B2, squeeze = _as2d(B)
     n, k = B2.shape
@@ -121,7 +125,7 @@ def pcg(X, B, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi", refine
         Xs = torch.empty_like(B2)
     xp = _dev(Xs, "x0", X.dtype, (p.n, k))
     o = _lib.PcgOpts(tol=float(tol), max_iter=int(max_iter),
-                     precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
+                     precond=_PRECOND[precond], rank=int(rank),
                      refine_every=int(refine_every), use_x0=1 if x0 is not None else 0,
                      check_every=int(check_every),
                      refine_prec={"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[refine_prec])
@@ -250,8 +254,7 @@ def gpr_predict(X, y, Xq, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jac
     xq = _dev(Xq, "Xq", X.dtype)
     mean = torch.empty(m, dtype=X.dtype, device=X.device)
     var = torch.empty(m, dtype=X.dtype, device=X.device) if want_var else None
-    o = _lib.PredictOpts(tol=float(tol), max_iter=int(max_iter),
-                         precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
+    o = _lib.PredictOpts(tol=float(tol), max_iter=int(max_iter), precond=_PRECOND[precond],
                          want_var=1 if want_var else 0, reserved=0)
     its = ctypes.c_int32()
     _lib.check(_lib.lib().higp_gpr_predict(
@@ -259,3 +262,15 @@ def gpr_predict(X, y, Xq, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jac
         ctypes.c_void_p(var.data_ptr()) if var is not None else None, ctypes.byref(its),
         _stream(stream, X.device)))
     return mean, var, dict(pcg_iters=its.value)
+
+
+def fps_landmarks(X, rank, stream=None):
+    """Indices (numpy int32) of the min(rank, n) farthest-point landmarks of
+    the Nyström preconditioner."""
+    p = problem(X, 0, 1.0, 1.0, 0.0)
+    r = min(int(rank), p.n)
+    idx = np.zeros(r, dtype=np.int32)
+    _lib.check(_lib.lib().higp_fps_landmarks(ctypes.byref(p), int(rank),
+                                            idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            _stream(stream, X.device)))
+    return idx

@@ -16,6 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhigp.so")
 SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f32_batch.hip", "kmatvec_f64.hip",
+           "nystrom.hip",
            "kmatvec_bf16.hip", "predict.hip", "blas.hip", "pcg.hip", "slq.hip", "nlml.hip",
            "server.hip"]
 ARCH = "gfx950"

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "nystrom.h"
 
 namespace higp {
 
@@ -180,8 +181,12 @@ int higp_pcg(const higp_problem* hp, int32_t k, const void* B, void* X, const hi
   if (!B || !X || !o) return set_error(HIGP_ERR_INVALID_ARG, "B, X and opts must be non-NULL");
   if (!(o->tol > 0.0)) return set_error(HIGP_ERR_INVALID_ARG, "tol must be > 0");
   if (o->max_iter < 1) return set_error(HIGP_ERR_INVALID_ARG, "max_iter must be >= 1");
-  if (o->precond != 0 && o->precond != 1)
-    return set_error(HIGP_ERR_INVALID_ARG, "precond must be 0 or 1");
+  if (o->precond < 0 || o->precond > 2)
+    return set_error(HIGP_ERR_INVALID_ARG, "precond must be 0, 1 or 2");
+  if (o->rank < 0 || o->rank > 2048)
+    return set_error(HIGP_ERR_INVALID_ARG, "rank must be in [0, 2048]");
+  if (o->precond == 2 && !(p.s > 0.0))
+    return set_error(HIGP_ERR_INVALID_ARG, "the Nyström preconditioner needs s > 0");
   if (o->refine_every < 0 || o->check_every < 0 || (o->use_x0 != 0 && o->use_x0 != 1))
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
   if (o->refine_prec != HIGP_FP64 && o->refine_prec != HIGP_FP32)
@@ -247,6 +252,17 @@ int higp_nlml(const higp_problem* hp, const void* y, int32_t nprobe, const void*
                   static_cast<hipStream_t>(stream));
 }
 
+int higp_fps_landmarks(const higp_problem* hp, int32_t rank, int32_t* idx, void* stream) {
+  clear_error();
+  Problem p;
+  HIGP_TRY(validate_problem(hp, &p));
+  if (p.prec != HIGP_FP64 && p.prec != HIGP_FP32 && p.prec != HIGP_BF16 && p.prec != HIGP_BF16X3)
+    return set_error(HIGP_ERR_INVALID_ARG, "unknown precision");
+  if (rank < 1 || rank > 2048) return set_error(HIGP_ERR_INVALID_ARG, "rank must be in [1, 2048]");
+  if (!idx) return set_error(HIGP_ERR_INVALID_ARG, "idx must be non-NULL");
+  return fps_landmarks(p, rank, idx, static_cast<hipStream_t>(stream));
+}
+
 int higp_kmatvec_cross(const higp_problem* hp, int64_t m, const void* Xq, int32_t k,
                        const void* V, void* Y, void* stream) {
   clear_error();
@@ -278,8 +294,9 @@ int higp_gpr_predict(const higp_problem* hp, const void* y, int64_t m, const voi
     return set_error(HIGP_ERR_INVALID_ARG, "m = %lld out of range", (long long)m);
   if (!y || !Xq || !o || !mean)
     return set_error(HIGP_ERR_INVALID_ARG, "y, Xq, opts and mean must be non-NULL");
-  if (!(o->tol > 0.0) || o->max_iter < 1 || (o->precond != 0 && o->precond != 1) ||
-      (o->want_var != 0 && o->want_var != 1) || o->reserved != 0)
+  if (!(o->tol > 0.0) || o->max_iter < 1 || o->precond < 0 || o->precond > 2 ||
+      (o->precond == 2 && !(p.s > 0.0)) || (o->want_var != 0 && o->want_var != 1) ||
+      o->reserved != 0)
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
   if ((o->want_var != 0) != (var != nullptr))
     return set_error(HIGP_ERR_INVALID_ARG, "var must be non-NULL exactly when want_var is 1");

@@ -1,0 +1,503 @@
+// Nyström preconditioner for PCG.  The paper's preconditioner (AFN) rests on
+// a Nyström approximation of the kernel matrix on selected points, and on
+// evaluating many small kernel matrices ("Statement of Need"); this is the
+// generic form:
+//
+//   landmarks  r points by farthest-point sampling (first point 0; each next
+//              one maximises the squared distance to the nearest landmark,
+//              lowest index on ties; distances in FP64);
+//   M          s·I + f²·K_nr·K_rr⁻¹·K_rn,  W = K_nr = k(X, X_landmarks; l);
+//   M⁻¹R       (R − W·C⁻¹·WᵀR)/s,           C = (s/f²)·K_rr + WᵀW  (Woodbury).
+//
+// Build: r − 1 fused "update nearest distance + argmax" launches; W in the
+// problem's precision (n×r, row-major); C accumulated in FP64 by a tiled
+// product; C⁻¹ by a host Cholesky factorisation (r ≤ 2048), stored in FP64.
+// Apply (once per PCG iteration): T = WᵀR by row chunks with FP64 partial
+// sums added in chunk order, u = C⁻¹T, Z = (R − W·u)/s.  Everything is
+// deterministic.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kvalue.h"
+#include "nystrom.h"
+
+namespace higp {
+namespace {
+
+constexpr int kThreads = 256;
+
+// dmin[i] = min(dmin[i], ‖x_i − x_p‖²) with p = sel[j − 1]; then the block
+// argmax (largest dmin, lowest index); the last block combines the blocks
+// and writes sel[j].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void fps_step(int64_t n, int d, const T* __restrict__ X,
+                                                     int* sel, int j, double* dmin,
+                                                     double* bval, int64_t* bidx,
+                                                     unsigned* counter) {
+  __shared__ double sv[kThreads];
+  __shared__ int64_t si[kThreads];
+  const int p = sel[j - 1];
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double dist = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double df = (double)X[i * d + c] - (double)X[(int64_t)p * d + c];
+      dist = dist + df * df;
+    }
+    const double m = fmin(dmin[i], dist);
+    dmin[i] = m;
+    if (m > best) {  // i increases along the loop: ties keep the lower index
+      best = m;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double v2 = sv[threadIdx.x + s];
+      const int64_t i2 = si[threadIdx.x + s];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bval[blockIdx.x] = sv[0];
+    bidx[blockIdx.x] = si[0];
+  }
+  __threadfence();
+  __syncthreads();
+  __shared__ unsigned ticket;
+  if (threadIdx.x == 0) ticket = atomicAdd(counter, 1u);
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double v = -1.0;
+    int64_t idx = 0;
+    for (unsigned b = 0; b < gridDim.x; ++b) {
+      const double vb = __hip_atomic_load(&bval[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int64_t ib = __hip_atomic_load(&bidx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (vb > v || (vb == v && ib < idx)) {
+        v = vb;
+        idx = ib;
+      }
+    }
+    sel[j] = (int)idx;
+    *counter = 0u;
+  }
+}
+
+__global__ void fill_inf(int64_t n, double* a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = HUGE_VAL;
+}
+
+// W[i][a] = k(x_i, x_sel[a]) in the problem's precision (pre-scaled points).
+template <typename T, int KERN>
+__global__ void nys_kernel_matrix(int64_t n, int r, int d, const T* __restrict__ X,
+                                  const int* __restrict__ sel, double xs, T* __restrict__ W) {
+  const int64_t total = n * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / r;
+    const int a = (int)(e % r);
+    const int64_t p = sel[a];
+    if constexpr (sizeof(T) == 8) {
+      double r2 = 0.0;
+      for (int c = 0; c < d; ++c) {
+        const double df = (X[i * d + c] - X[p * d + c]) * xs;
+        r2 = fma(df, df, r2);
+      }
+      double kv, kg;
+      kval_f64<KERN, false>(r2, kv, kg);
+      W[e] = (T)kv;
+    } else {
+      const float xsf = (float)xs;
+      float r2 = 0.0f;
+      for (int c = 0; c < d; ++c) {
+        const float df = ((float)X[i * d + c] - (float)X[p * d + c]) * xsf;
+        r2 = fmaf(df, df, r2);
+      }
+      float kv, kg;
+      kval_f32<KERN, false>(r2, kv, kg);
+      W[e] = (T)kv;
+    }
+  }
+}
+
+// part[s][a][b] = Σ_{i in chunk s} W[i][a]·W[i][b] for a 16×16 tile (FP64).
+constexpr int kGT = 16;   // tile edge
+constexpr int kGI = 32;   // rows staged per step
+template <typename T>
+__global__ __launch_bounds__(256) void nys_gram(int64_t n, int r, const T* __restrict__ W,
+                                                int64_t chunk, double* __restrict__ part) {
+  __shared__ double wa[kGI][kGT];
+  __shared__ double wb[kGI][kGT];
+  const int ta = threadIdx.x % kGT, tb = threadIdx.x / kGT;
+  const int a0 = blockIdx.x * kGT, b0 = blockIdx.y * kGT;
+  const int s = blockIdx.z;
+  const int64_t beg = (int64_t)s * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  for (int64_t i0 = beg; i0 < end; i0 += kGI) {
+    for (int e = threadIdx.x; e < kGI * kGT; e += 256) {
+      const int ii = e / kGT, cc = e % kGT;
+      const int64_t i = i0 + ii;
+      wa[ii][cc] = (i < end && a0 + cc < r) ? (double)W[i * r + a0 + cc] : 0.0;
+      wb[ii][cc] = (i < end && b0 + cc < r) ? (double)W[i * r + b0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int ii = 0; ii < kGI; ++ii) acc = fma(wa[ii][ta], wb[ii][tb], acc);
+    __syncthreads();
+  }
+  if (a0 + ta < r && b0 + tb < r) part[((int64_t)s * r + a0 + ta) * r + b0 + tb] = acc;
+}
+
+// C[a][b] = Σ_s part[s][a][b] + (s/f²)·W[sel[a]][b].
+template <typename T>
+__global__ void nys_gram_finish(int r, int S, const double* __restrict__ part,
+                                const T* __restrict__ W, const int* __restrict__ sel,
+                                double sf2, double* __restrict__ C) {
+  const int64_t total = (int64_t)r * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += part[(int64_t)s * total + e];
+    const int a = (int)(e / r), b = (int)(e % r);
+    C[e] = acc + sf2 * (double)W[(int64_t)sel[a] * r + b];
+  }
+}
+
+// part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c]; block: 64 landmarks ×
+// 4 column groups, rows of R staged in LDS.
+constexpr int kRI = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T* __restrict__ W,
+                                               const double* __restrict__ R, int64_t chunk,
+                                               double* __restrict__ part) {
+  __shared__ double rs[kRI][64];
+  const int la = threadIdx.x % 64, cg = threadIdx.x / 64;
+  const int a = blockIdx.x * 64 + la;
+  const int s = blockIdx.y;
+  const int64_t beg = (int64_t)s * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t i0 = beg; i0 < end; i0 += kRI) {
+    for (int e = threadIdx.x; e < kRI * 64; e += 256) {
+      const int ii = e / 64, c = e % 64;
+      const int64_t i = i0 + ii;
+      rs[ii][c] = (i < end && c < k) ? R[i * k + c] : 0.0;
+    }
+    __syncthreads();
+    const int rows = (int)std::min<int64_t>(kRI, end - i0);
+    for (int ii = 0; ii < rows; ++ii) {
+      const double w = a < r ? (double)W[(i0 + ii) * r + a] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = fma(w, rs[ii][cg + 4 * q], acc[q]);
+    }
+    __syncthreads();
+  }
+  if (a < r) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = cg + 4 * q;
+      if (c < k) part[((int64_t)s * r + a) * k + c] = acc[q];
+    }
+  }
+}
+
+// u[a][c] = Σ_b C⁻¹[a][b]·(Σ_s part[s][b][c]); T = Σ_s part is formed first.
+__global__ void nys_reduce_parts(int rk, int S, const double* __restrict__ part,
+                                 double* __restrict__ Tm) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rk; e += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += part[(int64_t)s * rk + e];
+    Tm[e] = acc;
+  }
+}
+
+__global__ void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
+                           const double* __restrict__ Tm, double* __restrict__ u) {
+  const int total = r * k;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int a = e / k, c = e % k;
+    double acc = 0.0;
+    for (int b = 0; b < r; ++b) acc = fma(Cinv[(int64_t)a * r + b], Tm[b * k + c], acc);
+    u[e] = acc;
+  }
+}
+
+// Z[i][c] = (R[i][c] − Σ_a W[i][a]·u[a][c]) / s.  Block: 64 rows × 4 column
+// groups; landmarks in chunks of 64 staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
+                                                   const T* __restrict__ W,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ R, double inv_s,
+                                                   double* __restrict__ Z) {
+  __shared__ double us[64][64];
+  __shared__ double ws[64][65];
+  const int lr = threadIdx.x % 64, cg = threadIdx.x / 64;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lr;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int a0 = 0; a0 < r; a0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int aa = e / 64, c = e % 64;
+      us[aa][c] = (a0 + aa < r && c < k) ? u[(a0 + aa) * k + c] : 0.0;
+      const int rr = e / 64, ac = e % 64;
+      const int64_t ir = (int64_t)blockIdx.x * 64 + rr;
+      ws[rr][ac] = (ir < n && a0 + ac < r) ? (double)W[ir * r + a0 + ac] : 0.0;
+    }
+    __syncthreads();
+    for (int aa = 0; aa < 64; ++aa) {
+      const double w = ws[lr][aa];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = fma(w, us[aa][cg + 4 * q], acc[q]);
+    }
+    __syncthreads();
+  }
+  if (i < n) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = cg + 4 * q;
+      if (c < k) Z[i * k + c] = (R[i * k + c] - acc[q]) * inv_s;
+    }
+  }
+}
+
+// In-place inverse of the SPD matrix A (r×r, row-major) by Cholesky:
+// A = LLᵀ, L⁻¹ by forward substitution, A⁻¹ = L⁻ᵀL⁻¹.  Returns false if A is
+// not numerically positive definite.
+bool spd_inverse(std::vector<double>& A, int r) {
+  std::vector<double> L((size_t)r * r, 0.0);
+  for (int i = 0; i < r; ++i) {
+    const double* li = &L[(size_t)i * r];
+    for (int j = 0; j <= i; ++j) {
+      const double* lj = &L[(size_t)j * r];
+      double s = A[(size_t)i * r + j];
+      for (int q = 0; q < j; ++q) s -= li[q] * lj[q];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[(size_t)i * r + i] = std::sqrt(s);
+      } else {
+        L[(size_t)i * r + j] = s / lj[j];
+      }
+    }
+  }
+  // M = L⁻¹ stored transposed: Mt[j][i] = (L⁻¹)[i][j] for i ≥ j.
+  std::vector<double> Mt((size_t)r * r, 0.0);
+  for (int j = 0; j < r; ++j) {
+    double* mj = &Mt[(size_t)j * r];
+    mj[j] = 1.0 / L[(size_t)j * r + j];
+    for (int i = j + 1; i < r; ++i) {
+      const double* li = &L[(size_t)i * r];
+      double s = 0.0;
+      for (int q = j; q < i; ++q) s += li[q] * mj[q];
+      mj[i] = -s / li[i];
+    }
+  }
+  // A⁻¹[a][b] = Σ_{i ≥ max(a,b)} L⁻¹[i][a]·L⁻¹[i][b] = Σ_i Mt[a][i]·Mt[b][i].
+  for (int a = 0; a < r; ++a) {
+    const double* ma = &Mt[(size_t)a * r];
+    for (int b = 0; b <= a; ++b) {
+      const double* mb = &Mt[(size_t)b * r];
+      double s = 0.0;
+      for (int i = a; i < r; ++i) s += ma[i] * mb[i];
+      A[(size_t)a * r + b] = s;
+      A[(size_t)b * r + a] = s;
+    }
+  }
+  return true;
+}
+
+unsigned grid_for(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+// Farthest-point landmarks into sel (device, r ints); dmin n doubles, bval/
+// bidx `blocks` slots each, counter one zero-initialised uint.
+template <typename T>
+int fps_select(const Problem& p, int r, int* sel, double* dmin, double* bval, int64_t* bidx,
+               unsigned* counter, int blocks, hipStream_t st) {
+  const int64_t n = p.n;
+  if (hipMemsetAsync(sel, 0, 4, st) != hipSuccess || hipMemsetAsync(counter, 0, 4, st) != hipSuccess)
+    return set_error(HIGP_ERR_HIP, "hipMemsetAsync failed");
+  hipLaunchKernelGGL(fill_inf, dim3(grid_for(n)), dim3(256), 0, st, n, dmin);
+  for (int j = 1; j < r; ++j)
+    hipLaunchKernelGGL((fps_step<T>), dim3(blocks), dim3(kThreads), 0, st, n, p.d,
+                       static_cast<const T*>(p.X), sel, j, dmin, bval, bidx, counter);
+  return hipGetLastError() == hipSuccess ? HIGP_OK
+                                         : set_error(HIGP_ERR_HIP, "landmark selection failed");
+}
+
+template <typename T>
+int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
+  const int64_t n = p.n;
+  auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int fps_blocks = (int)std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
+  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 4096));
+  const int64_t chunk = (n + S - 1) / S;
+  // Persistent part: W, C⁻¹, sel.  Work part (apply): partials, T, u.
+  const size_t w_bytes = rup((size_t)n * r * sizeof(T));
+  const size_t ci_bytes = rup((size_t)r * r * 8);
+  const size_t sel_bytes = rup((size_t)r * 4);
+  const size_t part_bytes = rup((size_t)S * r * kmax * 8);
+  const size_t t_bytes = rup((size_t)r * kmax * 8);
+  const size_t keep = w_bytes + ci_bytes + sel_bytes + part_bytes + 2 * t_bytes;
+  // Build-only scratch: dmin, block argmax slots, Gram partials and C.
+  const int gS = (int)std::max<int64_t>(1, std::min<int64_t>(8, n / 8192));
+  const int64_t gchunk = (n + gS - 1) / gS;
+  const size_t tmp_bytes = rup((size_t)n * 8) + rup((size_t)fps_blocks * 16) + 256 +
+                           rup((size_t)gS * r * r * 8) + rup((size_t)r * r * 8);
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, keep, st));
+  void* tmp = nullptr;
+  if (int rc = scratch_alloc(&tmp, tmp_bytes, st)) {
+    scratch_free(mem, st);
+    return rc;
+  }
+  char* base = static_cast<char*>(mem);
+  P->mem = mem;
+  P->n = n;
+  P->r = r;
+  P->kmax = kmax;
+  P->prec = p.prec;
+  P->s = p.s;
+  P->S = S;
+  P->chunk = chunk;
+  P->W = base;
+  P->Cinv = reinterpret_cast<double*>(base + w_bytes);
+  P->sel = reinterpret_cast<int*>(base + w_bytes + ci_bytes);
+  P->part = reinterpret_cast<double*>(base + w_bytes + ci_bytes + sel_bytes);
+  P->Tm = reinterpret_cast<double*>(base + w_bytes + ci_bytes + sel_bytes + part_bytes);
+  P->u = P->Tm + t_bytes / 8;
+  char* tb = static_cast<char*>(tmp);
+  double* dmin = reinterpret_cast<double*>(tb);
+  double* bval = reinterpret_cast<double*>(tb + rup((size_t)n * 8));
+  int64_t* bidx = reinterpret_cast<int64_t*>(bval + fps_blocks);
+  unsigned* counter =
+      reinterpret_cast<unsigned*>(tb + rup((size_t)n * 8) + rup((size_t)fps_blocks * 16));
+  double* gpart = reinterpret_cast<double*>(tb + rup((size_t)n * 8) +
+                                            rup((size_t)fps_blocks * 16) + 256);
+  double* C = gpart + rup((size_t)gS * r * r * 8) / 8;
+  auto fail = [&](int rc) {
+    scratch_free(tmp, st);
+    scratch_free(mem, st);
+    P->mem = nullptr;
+    return rc;
+  };
+  const T* X = static_cast<const T*>(p.X);
+  if (int rc = fps_select<T>(p, r, P->sel, dmin, bval, bidx, counter, fps_blocks, st))
+    return fail(rc);
+  // W = k(X, landmarks).
+  const double xs = coord_scale(p.kernel, sizeof(T) == 8 ? HIGP_FP64 : HIGP_FP32, p.l);
+  if (p.kernel == HIGP_GAUSSIAN)
+    hipLaunchKernelGGL((nys_kernel_matrix<T, HIGP_GAUSSIAN>), dim3(grid_for(n * r)), dim3(256), 0,
+                       st, n, r, p.d, X, (const int*)P->sel, xs, static_cast<T*>(P->W));
+  else
+    hipLaunchKernelGGL((nys_kernel_matrix<T, HIGP_MATERN32>), dim3(grid_for(n * r)), dim3(256),
+                       0, st, n, r, p.d, X, (const int*)P->sel, xs, static_cast<T*>(P->W));
+  // C = (s/f²)·K_rr + WᵀW.
+  const int tiles = (r + kGT - 1) / kGT;
+  hipLaunchKernelGGL((nys_gram<T>), dim3(tiles, tiles, gS), dim3(256), 0, st, n, r,
+                     (const T*)P->W, gchunk, gpart);
+  hipLaunchKernelGGL((nys_gram_finish<T>), dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, r,
+                     gS, (const double*)gpart, (const T*)P->W, (const int*)P->sel,
+                     p.s / (p.f * p.f), C);
+  if (hipGetLastError() != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "preconditioner build launch failed"));
+  std::vector<double> Ch((size_t)r * r);
+  if (hipMemcpyAsync(Ch.data(), C, Ch.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "copy of the Nyström core failed"));
+  if (!spd_inverse(Ch, r))
+    return fail(set_error(HIGP_ERR_INVALID_ARG,
+                          "Nyström core matrix is not positive definite (s too small?)"));
+  if (hipMemcpyAsync(P->Cinv, Ch.data(), Ch.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "upload of the Nyström core failed"));
+  scratch_free(tmp, st);
+  return HIGP_OK;
+}
+
+template <typename T>
+int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
+  const int ab = (P.r + 63) / 64;
+  hipLaunchKernelGGL((nys_wtr<T>), dim3(ab, P.S), dim3(256), 0, st, P.n, P.r, k,
+                     static_cast<const T*>(P.W), R, P.chunk, P.part);
+  const int rk = P.r * k;
+  hipLaunchKernelGGL(nys_reduce_parts, dim3(grid_for(rk)), dim3(256), 0, st, rk, P.S,
+                     (const double*)P.part, P.Tm);
+  hipLaunchKernelGGL(nys_cinv_t, dim3(grid_for(rk)), dim3(256), 0, st, P.r, k,
+                     (const double*)P.Cinv, (const double*)P.Tm, P.u);
+  hipLaunchKernelGGL((nys_apply_z<T>), dim3((unsigned)((P.n + 63) / 64)), dim3(256), 0, st, P.n,
+                     P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R, 1.0 / P.s, Z);
+  return hipGetLastError() == hipSuccess ? HIGP_OK
+                                         : set_error(HIGP_ERR_HIP, "preconditioner apply failed");
+}
+
+}  // namespace
+
+int nys_build(const Problem& p, int rank, int kmax, NysPrec* P, hipStream_t st) {
+  *P = NysPrec{};
+  const int r = (int)std::min<int64_t>(rank, p.n);
+  if (r < 1 || kmax < 1 || kmax > 64)
+    return set_error(HIGP_ERR_INVALID_ARG, "bad Nyström rank or width");
+  if (!(p.s > 0.0))
+    return set_error(HIGP_ERR_INVALID_ARG, "the Nyström preconditioner needs s > 0");
+  if (p.prec == HIGP_FP64) return build_impl<double>(p, r, kmax, P, st);
+  return build_impl<float>(p, r, kmax, P, st);
+}
+
+int nys_apply(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
+  if (k > P.kmax) return set_error(HIGP_ERR_INVALID_ARG, "Nyström apply wider than built");
+  if (P.prec == HIGP_FP64) return apply_impl<double>(P, k, R, Z, st);
+  return apply_impl<float>(P, k, R, Z, st);
+}
+
+int fps_landmarks(const Problem& p, int rank, int* sel_host, hipStream_t st) {
+  const int r = (int)std::min<int64_t>(rank, p.n);
+  const int blocks = (int)std::min<int64_t>(1024, (p.n + kThreads - 1) / kThreads);
+  auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bytes = rup((size_t)r * 4) + rup((size_t)p.n * 8) + rup((size_t)blocks * 16) + 256;
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, bytes, st));
+  char* b = static_cast<char*>(mem);
+  int* sel = reinterpret_cast<int*>(b);
+  double* dmin = reinterpret_cast<double*>(b + rup((size_t)r * 4));
+  double* bval = reinterpret_cast<double*>(b + rup((size_t)r * 4) + rup((size_t)p.n * 8));
+  int64_t* bidx = reinterpret_cast<int64_t*>(bval + blocks);
+  unsigned* counter = reinterpret_cast<unsigned*>(b + rup((size_t)r * 4) + rup((size_t)p.n * 8) +
+                                                  rup((size_t)blocks * 16));
+  int rc = p.prec == HIGP_FP64
+               ? fps_select<double>(p, r, sel, dmin, bval, bidx, counter, blocks, st)
+               : fps_select<float>(p, r, sel, dmin, bval, bidx, counter, blocks, st);
+  if (rc == HIGP_OK &&
+      (hipMemcpyAsync(sel_host, sel, (size_t)r * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    rc = set_error(HIGP_ERR_HIP, "landmark copy failed");
+  scratch_free(mem, st);
+  return rc;
+}
+
+void nys_free(NysPrec& P, hipStream_t st) {
+  if (P.mem) scratch_free(P.mem, st);
+  P.mem = nullptr;
+}
+
+}  // namespace higp

@@ -26,6 +26,7 @@
 // MatVec is used; the residual is then only as accurate as the FP32 floor.
 #include <vector>
 
+#include "nystrom.h"
 #include "pcg_kernels.h"
 
 namespace higp {
@@ -53,11 +54,13 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   const bool refine = o.refine_every > 0;
   const bool refine64 = refine && (o.refine_prec == HIGP_FP64 || p.prec == HIGP_FP64);
   const bool widen = refine64 && p.prec != HIGP_FP64;  // FP64 copy of the points
+  const bool nys = o.precond == 2;                      // Nyström preconditioner
   const size_t o_x = take(nk * 8), o_r = take(nk * 8), o_p = take(nk * sizeof(T)),
                o_q = take(nk * sizeof(T)),
                o_q2 = take(refine ? nk * (refine64 ? 8 : sizeof(T)) : 0),
                o_xd = take(widen ? (size_t)n * p.d * 8 : 0),
-               o_sc = take(9 * 64 * 8), o_int = take(4 * 64 * 4),
+               o_z = take(nys ? nk * 8 : 0), o_sc = take(10 * 64 * 8),
+               o_int = take(4 * 64 * 4),
                o_work = take(nwork * 8 * 2), o_cnt = take(2 * 4);
   void* mem = nullptr;
   HIGP_TRY(scratch_alloc(&mem, bytes, st));
@@ -97,6 +100,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   ps.tol = o.tol;
   ps.max_iter = o.max_iter;
   ps.minv = o.precond == 1 ? 1.0 / (p.f * p.f + p.s) : 1.0;
+  ps.general_m = nys ? 1 : 0;
   // Stopping only on a replaced residual is sound when the replacement is
   // accurate (FP64).  An FP32 replacement has a floor u₃₂·‖|K̂||x|‖/‖b‖ that
   // is usually above the tolerance; a column held open by it keeps taking
@@ -106,10 +110,18 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   ps.stall_off = refine && !refine64 ? 1 : 0;
 
   int rc = HIGP_OK;
+  NysPrec NP;
   auto fail = [&](int code) {
+    nys_free(NP, st);
     scratch_free(mem, st);
     return code;
   };
+  double* Z = nys ? (double*)(base + o_z) : nullptr;
+  double* rz = (double*)(base + o_sc) + 576;
+  if (nys) {
+    rc = nys_build(p, o.rank > 0 ? o.rank : (int)std::min<int64_t>(n, 1024), k, &NP, st);
+    if (rc) return fail(rc);
+  }
   if (hipMemsetAsync(S.counter, 0, 8, st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "hipMemsetAsync failed"));
   if (widen) {
@@ -133,8 +145,18 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   rc = launch_coldot(n, k, S.r, 0, S.r, 0, rr0, S.work, S.counter, st);
   if (rc) return fail(rc);
   hipLaunchKernelGGL(pcg_start_finish, dim3(1), dim3(64), 0, st, k, S, ps, bb, rr0);
-  hipLaunchKernelGGL((pcg_pinit<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S.r,
-                     ps.minv);
+  if (nys) {
+    // z₀ = M⁻¹r₀, ρ = r₀ᵀz₀, p = z₀.
+    rc = nys_apply(NP, k, S.r, Z, st);
+    if (rc == HIGP_OK) rc = launch_coldot(n, k, S.r, 0, Z, 0, rz, S.work, S.counter, st);
+    if (rc) return fail(rc);
+    hipLaunchKernelGGL(pcg_rho_beta, dim3(1), dim3(64), 0, st, k, S, (const double*)rz, 1);
+    rc = launch_cast_scale((int64_t)nk, Z, 0, P, wp, 1.0, st);
+    if (rc) return fail(rc);
+  } else {
+    hipLaunchKernelGGL((pcg_pinit<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S.r,
+                       ps.minv);
+  }
   if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
 
   int check = o.check_every > 0 ? o.check_every : (n >= 20000 ? 1 : 8);
@@ -181,8 +203,17 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
       if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     }
     after_replace = replace;
-    hipLaunchKernelGGL((pcg_pupdate<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S,
-                       ps.minv);
+    if (nys) {
+      rc = nys_apply(NP, k, S.r, Z, st);
+      if (rc == HIGP_OK) rc = launch_coldot(n, k, S.r, 0, Z, 0, rz, S.work, S.counter, st);
+      if (rc) return fail(rc);
+      hipLaunchKernelGGL(pcg_rho_beta, dim3(1), dim3(64), 0, st, k, S, (const double*)rz, 0);
+      hipLaunchKernelGGL((pcg_pupdate_z<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P,
+                         (const double*)Z, S);
+    } else {
+      hipLaunchKernelGGL((pcg_pupdate<T>), dim3(elem_blocks(nk)), dim3(256), 0, st, n, k, P, S,
+                         ps.minv);
+    }
     if (hipGetLastError() != hipSuccess) return fail(set_error(HIGP_ERR_HIP, "launch failed"));
     if (it % check == 0 || it == o.max_iter) {
       if (hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st) !=
@@ -206,6 +237,7 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "result copy failed"));
+  nys_free(NP, st);
   scratch_free(mem, st);
   for (int c = 0; c < k; ++c) {
     if (info && info->iters) info->iters[c] = it_h[c];

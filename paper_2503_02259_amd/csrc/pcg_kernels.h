@@ -45,6 +45,7 @@ struct PcgScalars {
   int max_iter;
   int replaced_only;  // 1: stop on tol only after a residual replacement
   int stall_off;      // 1: stop replacing a column once a replacement stalls
+  int general_m;      // 1: ρ = rᵀM⁻¹r comes from a separate dot (pcg_rho_beta)
 };
 
 // Finalisation shared by the update and replacement kernels: from ‖r_c‖²
@@ -60,9 +61,11 @@ __device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScala
   S.iters[c] = it;
   const double rel = S.bnorm[c] > 0.0 ? sqrt(rr) / S.bnorm[c] : 0.0;
   S.relres[c] = rel;
-  const double rho_new = P.minv * rr;
-  S.beta[c] = S.rho[c] != 0.0 ? rho_new / S.rho[c] : 0.0;
-  S.rho[c] = rho_new;
+  if (!P.general_m) {
+    const double rho_new = P.minv * rr;
+    S.beta[c] = S.rho[c] != 0.0 ? rho_new / S.rho[c] : 0.0;
+    S.rho[c] = rho_new;
+  }
   const bool tol_ok = rel <= P.tol && (replaced || !P.replaced_only);
   if (tol_ok || it >= P.max_iter || !(rel < 1e8)) S.active[c] = 0;
 }
@@ -147,6 +150,28 @@ __global__ __launch_bounds__(kRedThreads) void pcg_replace(int64_t n, int k, int
     }
   });
   if (last) pcg_count_active(S, k);
+}
+
+// General preconditioner: with rz = rᵀz (z = M⁻¹r), β = rz/ρ and ρ = rz for
+// the active columns (start: ρ = rz only).
+__global__ void pcg_rho_beta(int k, PcgState S, const double* __restrict__ rz, int start) {
+  const int c = threadIdx.x;
+  if (c < k && (start || S.active[c])) {
+    S.beta[c] = (!start && S.rho[c] != 0.0) ? rz[c] / S.rho[c] : 0.0;
+    S.rho[c] = rz[c];
+  }
+}
+
+// p = z + βp for active columns (general preconditioner; z FP64).
+template <typename T>
+__global__ void pcg_pupdate_z(int64_t n, int k, T* __restrict__ p, const double* __restrict__ z,
+                              PcgState S) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % k);
+    if (S.active[c]) p[e] = (T)(z[e] + S.beta[c] * (double)p[e]);
+  }
 }
 
 // p = M⁻¹r + βp for active columns (p in the MatVec precision).

@@ -73,8 +73,9 @@ def test_pcg_and_slq_reject_bad_options():
     L = _lib.lib()
     p = _prob()
     info = _lib.PcgInfo()
-    for kw in (dict(tol=0.0), dict(max_iter=0), dict(precond=2), dict(refine_every=-1),
-               dict(use_x0=3), dict(refine_prec=2), dict(check_every=-1)):
+    for kw in (dict(tol=0.0), dict(max_iter=0), dict(precond=3), dict(precond=-1),
+               dict(refine_every=-1), dict(use_x0=3), dict(refine_prec=2), dict(check_every=-1),
+               dict(precond=2, rank=-1), dict(precond=2, rank=4096)):
         o = _lib.PcgOpts(tol=1e-6, max_iter=10, precond=1, refine_every=0, use_x0=0,
                          check_every=0, refine_prec=0, x_fp64=None)
         for k, v in kw.items():
@@ -82,6 +83,16 @@ def test_pcg_and_slq_reject_bad_options():
         rc = L.higp_pcg(ctypes.byref(p), 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000),
                         ctypes.byref(o), ctypes.byref(info), None)
         assert rc == _lib.HIGP_ERR_INVALID_ARG, kw
+    # the Nyström preconditioner needs s > 0
+    o = _lib.PcgOpts(tol=1e-6, max_iter=10, precond=2, refine_every=0, use_x0=0, check_every=0,
+                     refine_prec=0, x_fp64=None, rank=16)
+    p0 = _prob(s=0.0)
+    assert L.higp_pcg(ctypes.byref(p0), 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x9000),
+                      ctypes.byref(o), ctypes.byref(info), None) == _lib.HIGP_ERR_INVALID_ARG
+    idx = (ctypes.c_int32 * 4)()
+    for rank in (0, -2, 2049):
+        assert L.higp_fps_landmarks(ctypes.byref(p), rank, idx, None) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_fps_landmarks(ctypes.byref(p), 4, None, None) == _lib.HIGP_ERR_INVALID_ARG
     ld = ctypes.c_double()
     for N, m, reo in ((0, 10, 1), (65, 10, 1), (4, 0, 1), (4, 2000, 1), (4, 10, 2)):
         rc = L.higp_slq_logdet(ctypes.byref(p), N, m, ctypes.c_void_p(0x2000), 0, reo, 1,
@@ -201,7 +212,7 @@ def test_gpr_predict_validation():
     y, xq, mean, var = (ctypes.c_void_p(v) for v in (0x2000, 0x100000, 0x900000, 0xA00000))
     good = dict(tol=1e-6, max_iter=50, precond=1, want_var=0, reserved=0)
     p = _prob()
-    for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=2), dict(want_var=2),
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=3), dict(want_var=2),
                 dict(reserved=1)):
         o = _lib.PredictOpts(**dict(good, **bad))
         rc = L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o), mean, None, None, None)
