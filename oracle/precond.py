@@ -8,10 +8,14 @@ not in the paper.  The generic form built here:
   * r landmark points chosen by farthest-point sampling: the first is point
     0, each next one is the point whose smallest squared distance to the
     landmarks chosen so far is largest (lowest index on ties);
-  * M = s·I + f²·K_nr K_rr⁻¹ K_rn with K_nr = k(X, X_landmarks; l);
+  * M = s·I + f²·K_nr (K_rr + εI)⁻¹ K_rn with K_nr = k(X, X_landmarks; l)
+    and ε = 1e-8: the jitter keeps K_rr invertible when landmarks sit much
+    closer than the length-scale (K_rr's spectrum then falls below the
+    rounding level); M stays symmetric positive definite;
   * M⁻¹ by the Woodbury identity with W = K_nr:
-      M⁻¹R = (R − W C⁻¹ WᵀR)/s,   C = (s/f²)·K_rr + WᵀW.
+      M⁻¹R = (R − W C⁻¹ WᵀR)/s,   C = (s/f²)·(K_rr + εI) + WᵀW.
 """
+JITTER = 1e-8
 import numpy as np
 
 from .kernels import sqdist, kernel_value
@@ -40,7 +44,7 @@ def nystrom_parts(X, kernel, l, f, s, r):
     X = np.asarray(X, dtype=np.float64)
     idx = fps_landmarks(X, r)
     W = kernel_value(sqdist(X, X[idx]), kernel, l)
-    C = (s / (f * f)) * W[idx] + W.T @ W
+    C = (s / (f * f)) * (W[idx] + JITTER * np.eye(len(idx))) + W.T @ W
     return W, C, idx
 
 
@@ -51,5 +55,6 @@ def nystrom_apply_inv(W, C, s, R):
 
 
 def nystrom_dense(W, idx, f, s):
-    """M itself (small n only): s·I + f²·W K_rr⁻¹ Wᵀ."""
-    return s * np.eye(W.shape[0]) + (f * f) * W @ np.linalg.solve(W[idx], W.T)
+    """M itself (small n only): s·I + f²·W (K_rr + εI)⁻¹ Wᵀ."""
+    Krr = W[idx] + JITTER * np.eye(len(idx))
+    return s * np.eye(W.shape[0]) + (f * f) * W @ np.linalg.solve(Krr, W.T)

@@ -6,15 +6,20 @@
 //   landmarks  r points by farthest-point sampling (first point 0; each next
 //              one maximises the squared distance to the nearest landmark,
 //              lowest index on ties; distances in FP64);
-//   M          s·I + f²·K_nr·K_rr⁻¹·K_rn,  W = K_nr = k(X, X_landmarks; l);
-//   M⁻¹R       (R − W·C⁻¹·WᵀR)/s,           C = (s/f²)·K_rr + WᵀW  (Woodbury).
+//   M          s·I + f²·K_nr·(K_rr + εI)⁻¹·K_rn, ε = 1e-8 (keeps K_rr
+//              invertible when landmarks sit closer than the length-scale);
+//   factor     K_rr + εI = RRᵀ (Cholesky), L = K_nr·R⁻ᵀ, so M = s·I + f²·LLᵀ;
+//   M⁻¹R       (R − L·C⁻¹·LᵀR)/s,  C = (s/f²)·I + LᵀL  (Woodbury; the
+//              eigenvalues of C are ≥ s/f², so C is well conditioned even
+//              when K_rr is not).
 //
-// Build: r − 1 fused "update nearest distance + argmax" launches; W in the
-// problem's precision (n×r, row-major); C accumulated in FP64 by a tiled
-// product; C⁻¹ by a host Cholesky factorisation (r ≤ 2048), stored in FP64.
-// Apply (once per PCG iteration): T = WᵀR by row chunks with FP64 partial
-// sums added in chunk order, u = C⁻¹T, Z = (R − W·u)/s.  Everything is
-// deterministic.
+// Build: r − 1 fused "update nearest distance + argmax" launches; K_nr in
+// the problem's precision (n×r, row-major); R⁻¹ by a host Cholesky
+// factorisation and triangular inverse (r ≤ 2048); L by a tiled product with
+// R⁻ᵀ (FP64 accumulation, stored in the problem's precision); C accumulated
+// in FP64 from that stored L; C⁻¹ on the host, stored in FP64.  Apply (once
+// per PCG iteration): T = LᵀR by row chunks with FP64 partial sums added in
+// chunk order, u = C⁻¹T, Z = (R − L·u)/s.  Everything is deterministic.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -26,6 +31,7 @@ namespace higp {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr double kNysJitter = 1e-8;  // ε added to the diagonal of K_rr
 
 // dmin[i] = min(dmin[i], ‖x_i − x_p‖²) with p = sel[j − 1]; then the block
 // argmax (largest dmin, lowest index); the last block combines the blocks
@@ -163,19 +169,81 @@ __global__ __launch_bounds__(256) void nys_gram(int64_t n, int r, const T* __res
   if (a0 + ta < r && b0 + tb < r) part[((int64_t)s * r + a0 + ta) * r + b0 + tb] = acc;
 }
 
-// C[a][b] = Σ_s part[s][a][b] + (s/f²)·W[sel[a]][b].
-template <typename T>
-__global__ void nys_gram_finish(int r, int S, const double* __restrict__ part,
-                                const T* __restrict__ W, const int* __restrict__ sel,
-                                double sf2, double* __restrict__ C) {
+// C[a][b] = Σ_s part[s][a][b] + (a == b ? s/f² : 0).
+__global__ void nys_gram_finish(int r, int S, const double* __restrict__ part, double sf2,
+                                double* __restrict__ C) {
   const int64_t total = (int64_t)r * r;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     double acc = 0.0;
     for (int s = 0; s < S; ++s) acc += part[(int64_t)s * total + e];
     const int a = (int)(e / r), b = (int)(e % r);
-    C[e] = acc + sf2 * (double)W[(int64_t)sel[a] * r + b];
+    C[e] = acc + (a == b ? sf2 : 0.0);
   }
+}
+
+// Krr[a][b] = W[sel[a]][b] (FP64): the landmark block of K_nr.
+template <typename T>
+__global__ void nys_gather_krr(int r, const T* __restrict__ W, const int* __restrict__ sel,
+                               double* __restrict__ Krr) {
+  const int64_t total = (int64_t)r * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / r), b = (int)(e % r);
+    Krr[e] = (double)W[(int64_t)sel[a] * r + b];
+  }
+}
+
+// L[i][a] = Σ_{b ≤ a} W[i][b]·Rinv[a][b] (L = W·R⁻ᵀ; Rinv lower triangular
+// with zeros above the diagonal).  64×64 output tiles, 4×4 per thread, b in
+// chunks of 16 up to the tile's last column.
+template <typename T>
+__global__ __launch_bounds__(256) void nys_tri_gemm(int64_t n, int r, const T* __restrict__ W,
+                                                    const double* __restrict__ Rinv,
+                                                    T* __restrict__ L) {
+  __shared__ double ws[16][65];
+  __shared__ double rs[16][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int a0 = blockIdx.y * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[q][t] = 0.0;
+  const int bmax = a0 + 64 < r ? a0 + 64 : r;
+  for (int b0 = 0; b0 < bmax; b0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int bb = e % 16, rr = e / 16;
+      const int64_t i = i0 + rr;
+      const int b = b0 + bb, a = a0 + rr;
+      ws[bb][rr] = (i < n && b < r) ? (double)W[i * r + b] : 0.0;
+      rs[bb][rr] = (a < r && b < r) ? Rinv[(int64_t)a * r + b] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int bb = 0; bb < 16; ++bb) {
+      double wv[4], rv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        wv[q] = ws[bb][ty * 4 + q];
+        rv[q] = rs[bb][tx * 4 + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[q][t] = fma(wv[q], rv[t], acc[q][t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t i = i0 + ty * 4 + q;
+      const int a = a0 + tx * 4 + t;
+      if (i < n && a < r) L[i * r + a] = (T)acc[q][t];
+    }
 }
 
 // part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c]; block: 64 landmarks ×
@@ -279,11 +347,10 @@ __global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
   }
 }
 
-// In-place inverse of the SPD matrix A (r×r, row-major) by Cholesky:
-// A = LLᵀ, L⁻¹ by forward substitution, A⁻¹ = L⁻ᵀL⁻¹.  Returns false if A is
-// not numerically positive definite.
-bool spd_inverse(std::vector<double>& A, int r) {
-  std::vector<double> L((size_t)r * r, 0.0);
+// Lower Cholesky factor of the SPD matrix A (r×r, row-major; zeros above
+// the diagonal).  Returns false if A is not numerically positive definite.
+bool chol_lower(const std::vector<double>& A, int r, std::vector<double>& L) {
+  L.assign((size_t)r * r, 0.0);
   for (int i = 0; i < r; ++i) {
     const double* li = &L[(size_t)i * r];
     for (int j = 0; j <= i; ++j) {
@@ -298,8 +365,13 @@ bool spd_inverse(std::vector<double>& A, int r) {
       }
     }
   }
-  // M = L⁻¹ stored transposed: Mt[j][i] = (L⁻¹)[i][j] for i ≥ j.
-  std::vector<double> Mt((size_t)r * r, 0.0);
+  return true;
+}
+
+// Inverse of the lower-triangular L, returned transposed: Mt[j][i] =
+// (L⁻¹)[i][j] (so column j of L⁻¹ is contiguous), zeros elsewhere.
+void tri_inverse_t(const std::vector<double>& L, int r, std::vector<double>& Mt) {
+  Mt.assign((size_t)r * r, 0.0);
   for (int j = 0; j < r; ++j) {
     double* mj = &Mt[(size_t)j * r];
     mj[j] = 1.0 / L[(size_t)j * r + j];
@@ -310,6 +382,14 @@ bool spd_inverse(std::vector<double>& A, int r) {
       mj[i] = -s / li[i];
     }
   }
+}
+
+// In-place inverse of the SPD matrix A (r×r, row-major): A = LLᵀ,
+// A⁻¹ = L⁻ᵀL⁻¹.  Returns false if A is not numerically positive definite.
+bool spd_inverse(std::vector<double>& A, int r) {
+  std::vector<double> L, Mt;
+  if (!chol_lower(A, r, L)) return false;
+  tri_inverse_t(L, r, Mt);
   // A⁻¹[a][b] = Σ_{i ≥ max(a,b)} L⁻¹[i][a]·L⁻¹[i][b] = Σ_i Mt[a][i]·Mt[b][i].
   for (int a = 0; a < r; ++a) {
     const double* ma = &Mt[(size_t)a * r];
@@ -352,18 +432,20 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   const int fps_blocks = (int)std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
   const int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 4096));
   const int64_t chunk = (n + S - 1) / S;
-  // Persistent part: W, C⁻¹, sel.  Work part (apply): partials, T, u.
-  const size_t w_bytes = rup((size_t)n * r * sizeof(T));
-  const size_t ci_bytes = rup((size_t)r * r * 8);
+  // Persistent part: L, C⁻¹, sel.  Work part (apply): partials, T, u.
+  const size_t l_bytes = rup((size_t)n * r * sizeof(T));
+  const size_t rr_bytes = rup((size_t)r * r * 8);
   const size_t sel_bytes = rup((size_t)r * 4);
   const size_t part_bytes = rup((size_t)S * r * kmax * 8);
   const size_t t_bytes = rup((size_t)r * kmax * 8);
-  const size_t keep = w_bytes + ci_bytes + sel_bytes + part_bytes + 2 * t_bytes;
-  // Build-only scratch: dmin, block argmax slots, Gram partials and C.
+  const size_t keep = l_bytes + rr_bytes + sel_bytes + part_bytes + 2 * t_bytes;
+  // Build-only scratch: K_nr, dmin, block argmax slots, K_rr / R⁻¹ / C
+  // (one r×r FP64 slot, reused), Gram partials.
   const int gS = (int)std::max<int64_t>(1, std::min<int64_t>(8, n / 8192));
   const int64_t gchunk = (n + gS - 1) / gS;
-  const size_t tmp_bytes = rup((size_t)n * 8) + rup((size_t)fps_blocks * 16) + 256 +
-                           rup((size_t)gS * r * r * 8) + rup((size_t)r * r * 8);
+  const size_t o_w = 0, o_dmin = o_w + l_bytes, o_bv = o_dmin + rup((size_t)n * 8),
+               o_cnt = o_bv + rup((size_t)fps_blocks * 16), o_rr = o_cnt + 256,
+               o_gp = o_rr + rr_bytes, tmp_bytes = o_gp + rup((size_t)gS * r * r * 8);
   void* mem = nullptr;
   HIGP_TRY(scratch_alloc(&mem, keep, st));
   void* tmp = nullptr;
@@ -381,20 +463,19 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   P->S = S;
   P->chunk = chunk;
   P->W = base;
-  P->Cinv = reinterpret_cast<double*>(base + w_bytes);
-  P->sel = reinterpret_cast<int*>(base + w_bytes + ci_bytes);
-  P->part = reinterpret_cast<double*>(base + w_bytes + ci_bytes + sel_bytes);
-  P->Tm = reinterpret_cast<double*>(base + w_bytes + ci_bytes + sel_bytes + part_bytes);
+  P->Cinv = reinterpret_cast<double*>(base + l_bytes);
+  P->sel = reinterpret_cast<int*>(base + l_bytes + rr_bytes);
+  P->part = reinterpret_cast<double*>(base + l_bytes + rr_bytes + sel_bytes);
+  P->Tm = reinterpret_cast<double*>(base + l_bytes + rr_bytes + sel_bytes + part_bytes);
   P->u = P->Tm + t_bytes / 8;
   char* tb = static_cast<char*>(tmp);
-  double* dmin = reinterpret_cast<double*>(tb);
-  double* bval = reinterpret_cast<double*>(tb + rup((size_t)n * 8));
+  T* Knr = reinterpret_cast<T*>(tb + o_w);
+  double* dmin = reinterpret_cast<double*>(tb + o_dmin);
+  double* bval = reinterpret_cast<double*>(tb + o_bv);
   int64_t* bidx = reinterpret_cast<int64_t*>(bval + fps_blocks);
-  unsigned* counter =
-      reinterpret_cast<unsigned*>(tb + rup((size_t)n * 8) + rup((size_t)fps_blocks * 16));
-  double* gpart = reinterpret_cast<double*>(tb + rup((size_t)n * 8) +
-                                            rup((size_t)fps_blocks * 16) + 256);
-  double* C = gpart + rup((size_t)gS * r * r * 8) / 8;
+  unsigned* counter = reinterpret_cast<unsigned*>(tb + o_cnt);
+  double* RR = reinterpret_cast<double*>(tb + o_rr);
+  double* gpart = reinterpret_cast<double*>(tb + o_gp);
   auto fail = [&](int rc) {
     scratch_free(tmp, st);
     scratch_free(mem, st);
@@ -404,31 +485,47 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   const T* X = static_cast<const T*>(p.X);
   if (int rc = fps_select<T>(p, r, P->sel, dmin, bval, bidx, counter, fps_blocks, st))
     return fail(rc);
-  // W = k(X, landmarks).
+  // K_nr = k(X, landmarks).
   const double xs = coord_scale(p.kernel, sizeof(T) == 8 ? HIGP_FP64 : HIGP_FP32, p.l);
   if (p.kernel == HIGP_GAUSSIAN)
     hipLaunchKernelGGL((nys_kernel_matrix<T, HIGP_GAUSSIAN>), dim3(grid_for(n * r)), dim3(256), 0,
-                       st, n, r, p.d, X, (const int*)P->sel, xs, static_cast<T*>(P->W));
+                       st, n, r, p.d, X, (const int*)P->sel, xs, Knr);
   else
     hipLaunchKernelGGL((nys_kernel_matrix<T, HIGP_MATERN32>), dim3(grid_for(n * r)), dim3(256),
-                       0, st, n, r, p.d, X, (const int*)P->sel, xs, static_cast<T*>(P->W));
-  // C = (s/f²)·K_rr + WᵀW.
+                       0, st, n, r, p.d, X, (const int*)P->sel, xs, Knr);
+  // K_rr + εI = RRᵀ on the host, R⁻¹ back to the device.
+  hipLaunchKernelGGL((nys_gather_krr<T>), dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, r,
+                     (const T*)Knr, (const int*)P->sel, RR);
+  if (hipGetLastError() != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "preconditioner build launch failed"));
+  std::vector<double> A((size_t)r * r), F, Mt;
+  if (hipMemcpyAsync(A.data(), RR, A.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "copy of the landmark block failed"));
+  for (int a = 0; a < r; ++a) A[(size_t)a * r + a] += kNysJitter;
+  if (!chol_lower(A, r, F))
+    return fail(set_error(HIGP_ERR_INVALID_ARG, "landmark kernel block is not positive definite"));
+  tri_inverse_t(F, r, Mt);
+  for (int a = 0; a < r; ++a)  // R⁻¹[a][b] = Mt[b][a] (lower triangular)
+    for (int b = 0; b < r; ++b) A[(size_t)a * r + b] = b <= a ? Mt[(size_t)b * r + a] : 0.0;
+  if (hipMemcpyAsync(RR, A.data(), A.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(set_error(HIGP_ERR_HIP, "upload of the landmark factor failed"));
+  // L = K_nr·R⁻ᵀ, then C = (s/f²)·I + LᵀL.
+  hipLaunchKernelGGL((nys_tri_gemm<T>), dim3((unsigned)((n + 63) / 64), (r + 63) / 64), dim3(256),
+                     0, st, n, r, (const T*)Knr, (const double*)RR, static_cast<T*>(P->W));
   const int tiles = (r + kGT - 1) / kGT;
   hipLaunchKernelGGL((nys_gram<T>), dim3(tiles, tiles, gS), dim3(256), 0, st, n, r,
                      (const T*)P->W, gchunk, gpart);
-  hipLaunchKernelGGL((nys_gram_finish<T>), dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, r,
-                     gS, (const double*)gpart, (const T*)P->W, (const int*)P->sel,
-                     p.s / (p.f * p.f), C);
+  hipLaunchKernelGGL(nys_gram_finish, dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, r, gS,
+                     (const double*)gpart, p.s / (p.f * p.f), RR);
   if (hipGetLastError() != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "preconditioner build launch failed"));
-  std::vector<double> Ch((size_t)r * r);
-  if (hipMemcpyAsync(Ch.data(), C, Ch.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(A.data(), RR, A.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "copy of the Nyström core failed"));
-  if (!spd_inverse(Ch, r))
-    return fail(set_error(HIGP_ERR_INVALID_ARG,
-                          "Nyström core matrix is not positive definite (s too small?)"));
-  if (hipMemcpyAsync(P->Cinv, Ch.data(), Ch.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+  if (!spd_inverse(A, r))
+    return fail(set_error(HIGP_ERR_INVALID_ARG, "Nyström core matrix is not positive definite"));
+  if (hipMemcpyAsync(P->Cinv, A.data(), A.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "upload of the Nyström core failed"));
   scratch_free(tmp, st);
