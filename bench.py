@@ -90,6 +90,8 @@ def main():
                     help="comma list of extra legs (fp64, bf16, grad, train, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
+    ap.add_argument("--serve-rank", type=int, default=256,
+                    help="Nyström rank of the second serving replay")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
                     help="time only this form's MatVec on the n=500,000 d=8 mixture "
                          "(for profiling) and print its own JSON line")
@@ -240,6 +242,7 @@ def main():
         out["train_e2e"] = leg_train()
     if "serve" in legs and args.serve > 0:
         out["serving"] = leg_serve(args.serve)
+        out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
@@ -394,10 +397,11 @@ def leg_train():
                 loss_first=hist[0]["loss"], loss_last=hist[-1]["loss"], theta_final=model.get_params())
 
 
-def leg_serve(nreq):
+def leg_serve(nreq, precond_rank=0):
     """Continuous batching: the first `nreq` requests of the Poisson stream
     (rate 200/s; n log-uniform in [1e3, 2e5]; d ∈ {2,3,8}; l ~ U[0.05,0.5];
-    s = 1e-2; FP32), each CG to 1e-6 + SLQ 16 probes × 40 steps."""
+    s = 1e-2; FP32), each CG to 1e-6 (Jacobi, or the Nyström preconditioner
+    of rank `precond_rank`) + SLQ 16 probes × 40 steps."""
     import torch
     from paper_2503_02259_amd import workloads as W
     from paper_2503_02259_amd.serve import Server, replay
@@ -415,9 +419,12 @@ def leg_serve(nreq):
         _log("serve: %d/%d done (request %d, %d CG iterations)" % (len(stats), nreq, i, st.iters))
 
     srv = Server(hbm_budget=128 << 30, max_active=64)
-    r = replay(reqs, srv, upload, tol=1e-6, max_iter=1000, nsteps=40, on_done=done)
+    r = replay(reqs, srv, upload, tol=1e-6, max_iter=1000, nsteps=40, on_done=done,
+               precond_rank=precond_rank)
     srv.close()
-    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 + SLQ 16x40, FP32" % nreq,
+    pc = "Nystrom rank %d" % precond_rank if precond_rank else "Jacobi"
+    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 (%s) + SLQ 16x40, FP32"
+                         % (nreq, pc),
                 requests=nreq, p50_s=r["p50"], p99_s=r["p99"], solves_per_s=r["throughput"],
                 span_s=r["span"], cg_iters_mean=float(np.mean([x[0] for x in stats])),
                 converged=int(sum(x[1] for x in stats)))

@@ -286,7 +286,9 @@ typedef struct {
   int32_t nsteps;      /* Lanczos steps (1..1024) when nprobe > 0 */
   double tol;          /* CG tolerance (> 0) */
   int32_t max_iter;    /* CG iteration cap (≥ 1) */
-  int32_t reserved;    /* must be 0 */
+  int32_t precond_rank; /* 0: Jacobi; 1 … 2048: the Nyström preconditioner of
+                           higp_pcg (precond 2) with that many landmarks (clamped
+                           to n; needs s > 0), built when the request is admitted */
   void* x_out;         /* device n float: receives x = K̂⁻¹y when the request is done */
 } higp_request;
 
@@ -307,8 +309,10 @@ typedef struct {
 } higp_request_status;
 
 /* Device bytes the server reserves for a request (state, vectors, Lanczos
- * basis, batch partials).  Host only; 0 for invalid sizes.                  */
-uint64_t higp_request_footprint(int64_t n, int32_t d, int32_t nprobe, int32_t nsteps);
+ * basis, batch partials, and the Nyström factor when precond_rank > 0).
+ * Host only; 0 for invalid sizes.                                          */
+uint64_t higp_request_footprint(int64_t n, int32_t d, int32_t nprobe, int32_t nsteps,
+                                int32_t precond_rank);
 
 int higp_server_create(const higp_server_opts* opts, higp_server** server);
 /* Queue a request; the caller's buffers (X, y, Z, x_out) must stay valid until

@@ -73,7 +73,7 @@ class ServerOpts(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("p", Problem), ("y", ctypes.c_void_p), ("Z", ctypes.c_void_p),
                 ("nprobe", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("precond_rank", ctypes.c_int32),
                 ("x_out", ctypes.c_void_p)]
 
 
@@ -116,7 +116,7 @@ def lib():
         L.higp_slq_logdet.argtypes = [PP, i32, i32, vp, ctypes.c_uint64, i32, i32, dp, dp, vp]
         L.higp_tridiag_eig.argtypes = [i32, dp, dp, dp, dp]
         L.higp_coldot.argtypes = [i64, i32, i32, vp, i32, vp, dp, vp]
-        L.higp_request_footprint.argtypes = [i64, i32, i32, i32]
+        L.higp_request_footprint.argtypes = [i64, i32, i32, i32, i32]
         L.higp_request_footprint.restype = ctypes.c_uint64
         L.higp_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
         L.higp_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]

@@ -26,6 +26,8 @@ int nys_build(const Problem& p, int rank, int kmax, NysPrec* P, hipStream_t st);
 // Z = M⁻¹R for an n×k FP64 block (k ≤ kmax); asynchronous.
 int nys_apply(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st);
 void nys_free(NysPrec& P, hipStream_t st);
+// Device bytes a built preconditioner holds (kept until nys_free).
+size_t nys_bytes(int64_t n, int rank, int kmax, int prec);
 // The min(rank, n) farthest-point landmarks into host memory; synchronises.
 int fps_landmarks(const Problem& p, int rank, int* sel_host, hipStream_t st);
 

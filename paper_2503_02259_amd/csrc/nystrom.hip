@@ -567,6 +567,15 @@ int nys_apply(const NysPrec& P, int k, const double* R, double* Z, hipStream_t s
   return apply_impl<float>(P, k, R, Z, st);
 }
 
+size_t nys_bytes(int64_t n, int rank, int kmax, int prec) {
+  const int r = (int)std::min<int64_t>(rank, n);
+  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 4096));
+  auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t es = prec == HIGP_FP64 ? 8 : 4;
+  return rup((size_t)n * r * es) + rup((size_t)r * r * 8) + rup((size_t)r * 4) +
+         rup((size_t)S * r * kmax * 8) + 2 * rup((size_t)r * kmax * 8);
+}
+
 int fps_landmarks(const Problem& p, int rank, int* sel_host, hipStream_t st) {
   const int r = (int)std::min<int64_t>(rank, p.n);
   const int blocks = (int)std::min<int64_t>(1024, (p.n + kThreads - 1) / kThreads);

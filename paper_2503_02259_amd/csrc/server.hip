@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "lanczos_kernels.h"
+#include "nystrom.h"
 #include "pcg_kernels.h"
 
 namespace higp {
@@ -70,7 +71,8 @@ struct Request {
   higp_request req{};
   Problem p{};
   int state = HIGP_REQ_QUEUED;
-  size_t footprint = 0;
+  size_t footprint = 0;   // state bytes + Nyström factor bytes (admission budget)
+  size_t state_bytes = 0; // the part allocated as r.mem
   void* mem = nullptr;
   // device state
   float* Xp = nullptr;
@@ -87,6 +89,9 @@ struct Request {
   unsigned* counter2 = nullptr;
   PcgState S{};
   PcgScalars ps{};
+  NysPrec np{};           // Nyström preconditioner (precond_rank > 0)
+  double* z = nullptr;    // M⁻¹r (Nyström)
+  double* rz = nullptr;   // rᵀM⁻¹r
   LzState L{};
   int N = 0, m = 0;
   int slot = -1;          // index into the pinned status array
@@ -97,7 +102,7 @@ struct Request {
   higp_request_status out{};
 };
 
-size_t request_footprint(int64_t n, int d, int N, int m) {
+size_t request_footprint(int64_t n, int d, int N, int m, int rank) {
   const int kmax = 1 + N;
   const size_t nk_pad = ((size_t)n * kmax + 3) / 4 * 4;
   const RedGrid g = red_grid(n);
@@ -108,6 +113,7 @@ size_t request_footprint(int64_t n, int d, int N, int m) {
     b += lz_state_bytes(n, N, m) + 2 * rup((size_t)n * N * 4) + rup(64 * 8);  // Lanczos, QW, WW, zn2
   }
   b += (size_t)batch_splits(n) * n * kmax * 4;                         // batch partials
+  if (rank > 0) b += nys_bytes(n, rank, 1, HIGP_FP32) + rup((size_t)n * 8) + rup(64);
   return b;
 }
 
@@ -130,7 +136,7 @@ int admit(Server& sv, Request& r) {
   const int N = r.N, m = r.m;
   const int kmax = 1 + N;
   const size_t nk_pad = ((size_t)n * kmax + 3) / 4 * 4;
-  HIGP_TRY(scratch_alloc(&r.mem, r.footprint, sv.st));
+  HIGP_TRY(scratch_alloc(&r.mem, r.state_bytes, sv.st));
   char* base = static_cast<char*>(r.mem);
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -146,6 +152,10 @@ int admit(Server& sv, Request& r) {
   r.S.r = (double*)take((size_t)n * 8);
   r.cg_p = (float*)take((size_t)n * 4);
   r.cg_q = (float*)take((size_t)n * 4);
+  if (r.req.precond_rank > 0) {
+    r.z = (double*)take((size_t)n * 8);
+    r.rz = (double*)take(64);
+  }
   double* sc = (double*)take(8 * 64 * 8);
   r.S.rho = sc;
   r.S.pq = sc + 64;
@@ -169,7 +179,7 @@ int admit(Server& sv, Request& r) {
     r.WW = (float*)take((size_t)n * N * 4);
     r.zn2 = (double*)take(64 * 8);
   }
-  if (off > r.footprint) return set_error(HIGP_ERR_HIP, "internal: footprint underestimated");
+  if (off > r.state_bytes) return set_error(HIGP_ERR_HIP, "internal: footprint underestimated");
 
   r.slot = sv.free_slots.back();
   sv.free_slots.pop_back();
@@ -197,6 +207,15 @@ int admit(Server& sv, Request& r) {
                      (const double*)r.rr0);
   hipLaunchKernelGGL((pcg_pinit<float>), dim3(elem_blocks(n)), dim3(256), 0, st, n, 1, r.cg_p,
                      (const double*)r.S.r, r.ps.minv);
+  if (r.req.precond_rank > 0) {
+    // Nyström: z₀ = M⁻¹r₀, ρ = r₀ᵀz₀, p = z₀ (replaces p = M⁻¹r₀ with Jacobi).
+    HIGP_TRY(nys_build(r.p, r.req.precond_rank, 1, &r.np, st));
+    r.ps.general_m = 1;
+    HIGP_TRY(nys_apply(r.np, 1, r.S.r, r.z, st));
+    HIGP_TRY(launch_coldot(n, 1, r.S.r, 0, r.z, 0, r.rz, r.S.work, r.S.counter, st));
+    hipLaunchKernelGGL(pcg_rho_beta, dim3(1), dim3(64), 0, st, 1, r.S, (const double*)r.rz, 1);
+    HIGP_TRY(launch_cast_scale(n, r.z, 0, r.cg_p, 1, 1.0, st));
+  }
   r.cg_active = true;
   // Lanczos start: q₀ = z/‖z‖ on K̂/(f²+s).
   if (N > 0) {
@@ -269,6 +288,7 @@ int retire(Server& sv, Request& r) {
   r.out.rounds = r.rounds;
   r.out.state = rc == HIGP_OK ? HIGP_REQ_DONE : HIGP_REQ_FAILED;
   r.state = r.out.state;
+  nys_free(r.np, st);
   scratch_free(r.mem, st);
   r.mem = nullptr;
   sv.used -= r.footprint;
@@ -288,6 +308,7 @@ int run_round(Server& sv) {
     const int rc = admit(sv, *r);
     if (rc != HIGP_OK) {
       r->state = r->out.state = HIGP_REQ_FAILED;
+      nys_free(r->np, st);
       if (r->mem) scratch_free(r->mem, st);
       r->mem = nullptr;
       sv.used -= r->footprint;
@@ -342,8 +363,16 @@ int run_round(Server& sv) {
       hipLaunchKernelGGL((pcg_update<float>), dim3(g.blocks), dim3(kRedThreads), 0, st, n, 1,
                          g.chunk, (const float*)r.cg_p, (const float*)r.cg_q, r.S, r.ps, 1,
                          (const double*)nullptr);
-      hipLaunchKernelGGL((pcg_pupdate<float>), dim3(elem_blocks(n)), dim3(256), 0, st, n, 1,
-                         r.cg_p, r.S, r.ps.minv);
+      if (r.np.mem) {
+        HIGP_TRY(nys_apply(r.np, 1, r.S.r, r.z, st));
+        HIGP_TRY(launch_coldot(n, 1, r.S.r, 0, r.z, 0, r.rz, r.S.work, r.S.counter, st));
+        hipLaunchKernelGGL(pcg_rho_beta, dim3(1), dim3(64), 0, st, 1, r.S, (const double*)r.rz, 0);
+        hipLaunchKernelGGL((pcg_pupdate_z<float>), dim3(elem_blocks(n)), dim3(256), 0, st, n, 1,
+                           r.cg_p, (const double*)r.z, r.S);
+      } else {
+        hipLaunchKernelGGL((pcg_pupdate<float>), dim3(elem_blocks(n)), dim3(256), 0, st, n, 1,
+                           r.cg_p, r.S, r.ps.minv);
+      }
     }
     if (lz) {
       const double isq = 1.0 / std::sqrt(r.p.f * r.p.f + r.p.s);
@@ -394,9 +423,15 @@ using namespace higp;
 
 extern "C" {
 
-uint64_t higp_request_footprint(int64_t n, int32_t d, int32_t nprobe, int32_t nsteps) {
-  if (n < 1 || d < 1 || d > HIGP_MAX_D || nprobe < 0 || nprobe > 31 || nsteps < 0) return 0;
-  return (uint64_t)request_footprint(n, d, nprobe, nprobe > 0 ? nsteps : 0);
+uint64_t higp_request_footprint(int64_t n, int32_t d, int32_t nprobe, int32_t nsteps,
+                                int32_t precond_rank) {
+  if (n < 1 || d < 1 || d > HIGP_MAX_D || nprobe < 0 || nprobe > 31 || nsteps < 0 ||
+      precond_rank < 0 || precond_rank > 2048)
+    return 0;
+  const int m = nprobe > 0 ? nsteps : 0;
+  return (uint64_t)(request_footprint(n, d, nprobe, m, 0) +
+                    (precond_rank > 0 ? request_footprint(n, d, nprobe, m, precond_rank) -
+                                            request_footprint(n, d, nprobe, m, 0) : 0));
 }
 
 int higp_server_create(const higp_server_opts* o, higp_server** out) {
@@ -436,15 +471,21 @@ int higp_server_submit(higp_server* h, const higp_request* rq, int64_t* id) {
   if (rq->nprobe < 0 || rq->nprobe > 31 || (rq->nprobe > 0 && (!rq->Z || rq->nsteps < 1 ||
                                                                rq->nsteps > 1024)))
     return set_error(HIGP_ERR_INVALID_ARG, "bad probe settings (0 <= nprobe <= 31)");
-  if (!(rq->tol > 0.0) || rq->max_iter < 1 || rq->reserved != 0)
+  if (!(rq->tol > 0.0) || rq->max_iter < 1)
     return set_error(HIGP_ERR_INVALID_ARG, "bad CG settings");
+  if (rq->precond_rank < 0 || rq->precond_rank > 2048 || (rq->precond_rank > 0 && !(p.s > 0.0)))
+    return set_error(HIGP_ERR_INVALID_ARG, "precond_rank must be in [0, 2048] (and s > 0 for > 0)");
   auto r = std::make_unique<Request>();
   r->id = sv.next_id++;
   r->req = *rq;
   r->p = p;
   r->N = rq->nprobe;
   r->m = rq->nprobe > 0 ? rq->nsteps : 0;
-  r->footprint = request_footprint(p.n, p.d, r->N, r->m);
+  const int rank = rq->precond_rank;
+  // State (one allocation) and, with Nyström, the factor nys_build allocates.
+  r->state_bytes = request_footprint(p.n, p.d, r->N, r->m, 0) +
+                   (rank > 0 ? ((size_t)p.n * 8 + 255) / 256 * 256 + 256 : 0);
+  r->footprint = request_footprint(p.n, p.d, r->N, r->m, rank);
   r->out.state = HIGP_REQ_QUEUED;
   if (r->footprint > sv.opts.hbm_budget)
     return set_error(HIGP_ERR_OOM, "request needs %zu bytes, more than the server budget",
@@ -480,8 +521,10 @@ int higp_server_destroy(higp_server* h) {
   clear_error();
   if (!h) return HIGP_OK;
   Server* sv = reinterpret_cast<Server*>(h);
-  for (auto& r : sv->active)
+  for (auto& r : sv->active) {
+    nys_free(r->np, sv->st);
     if (r->mem) scratch_free(r->mem, sv->st);
+  }
   (void)hipStreamSynchronize(sv->st);
   if (sv->status_h) (void)hipHostFree(sv->status_h);
   if (sv->status_d) (void)hipFree(sv->status_d);

@@ -31,16 +31,19 @@ class Server:
         self._keep = {}
 
     def submit(self, X, y, Z=None, l=0.1, f=1.0, s=1e-2, kernel=0, tol=1e-6, max_iter=1000,
-               nsteps=40):
+               nsteps=40, precond_rank=0):
         """Queue a solve; returns its id.  X (n×d), y (n), Z (n×nprobe) are
-        float32 device tensors kept alive until the request is done."""
+        float32 device tensors kept alive until the request is done.
+        precond_rank > 0 solves with the Nyström preconditioner of that rank
+        instead of Jacobi."""
         p = problem(X, kernel, l, f, s, "fp32")
         x_out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
         nprobe = 0 if Z is None else Z.shape[1]
         r = _lib.Request(p=p, y=_dev(y, "y", torch.float32, (X.shape[0],)),
                          Z=_dev(Z, "Z", torch.float32) if Z is not None else None,
                          nprobe=nprobe, nsteps=int(nsteps) if nprobe else 0, tol=float(tol),
-                         max_iter=int(max_iter), reserved=0, x_out=ctypes.c_void_p(x_out.data_ptr()))
+                         max_iter=int(max_iter), precond_rank=int(precond_rank),
+                         x_out=ctypes.c_void_p(x_out.data_ptr()))
         rid = ctypes.c_int64()
         _lib.check(_lib.lib().higp_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
         self._keep[rid.value] = (X, y, Z, x_out)
@@ -75,12 +78,12 @@ class Server:
             pass
 
 
-def footprint(n, d, nprobe, nsteps):
-    return int(_lib.lib().higp_request_footprint(n, d, nprobe, nsteps))
+def footprint(n, d, nprobe, nsteps, precond_rank=0):
+    return int(_lib.lib().higp_request_footprint(n, d, nprobe, nsteps, precond_rank))
 
 
 def replay(requests, server, upload, tol=1e-6, max_iter=1000, nsteps=40, time_scale=1.0,
-           on_done=None):
+           on_done=None, precond_rank=0):
     """Open-loop replay: request i is submitted once the wall clock passes its
     arrival time (× time_scale).  ``upload(req)`` returns the device tensors
     (X, y, Z) of a request (done at arrival, outside the server).  Returns a
@@ -95,7 +98,8 @@ def replay(requests, server, upload, tol=1e-6, max_iter=1000, nsteps=40, time_sc
         while nxt < n_req and requests[nxt].arrival * time_scale <= now:
             r = requests[nxt]
             X, y, Z = upload(r)
-            ids[server.submit(X, y, Z, l=r.l, tol=tol, max_iter=max_iter, nsteps=nsteps)] = nxt
+            ids[server.submit(X, y, Z, l=r.l, tol=tol, max_iter=max_iter, nsteps=nsteps,
+                              precond_rank=precond_rank)] = nxt
             nxt += 1
         na, nq = server.step() if ids else (0, 0)
         now = time.perf_counter() - t0

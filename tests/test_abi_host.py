@@ -182,7 +182,7 @@ def test_coldot_and_nlml_reject_bad_arguments():
 
 def test_request_footprint_host_logic():
     L = _lib.lib()
-    f = lambda n, d, N, m: int(L.higp_request_footprint(n, d, N, m))
+    f = lambda n, d, N, m, r=0: int(L.higp_request_footprint(n, d, N, m, r))
     assert f(0, 3, 16, 40) == 0 and f(100, 9, 16, 40) == 0 and f(100, 3, 32, 40) == 0
     a, b = f(10_000, 3, 16, 40), f(20_000, 3, 16, 40)
     assert 0 < a < b
@@ -190,6 +190,9 @@ def test_request_footprint_host_logic():
     assert b >= 41 * 20_000 * 16 * 8
     assert f(10_000, 3, 16, 40) < f(10_000, 3, 16, 80)
     assert f(10_000, 3, 0, 40) < a
+    # the Nyström factor adds at least n·rank floats and n doubles for z
+    assert f(10_000, 3, 16, 40, 128) >= a + 10_000 * 128 * 4 + 10_000 * 8
+    assert f(10_000, 3, 16, 40, 4096) == 0 and f(10_000, 3, 16, 40, -1) == 0
 
 
 def test_kmatvec_cross_validation():

@@ -26,8 +26,9 @@ def _upload(X, y, Z):
             to_dev(Z, torch.float32) if Z is not None else None)
 
 
-def _run(server, reqs, l=0.2):
-    ids = [server.submit(*_upload(*r), l=l, tol=1e-6, max_iter=1000, nsteps=30) for r in reqs]
+def _run(server, reqs, l=0.2, precond_rank=0):
+    ids = [server.submit(*_upload(*r), l=l, tol=1e-6, max_iter=1000, nsteps=30,
+                         precond_rank=precond_rank) for r in reqs]
     for _ in range(100000):
         na, nq = server.step()
         if na == 0 and nq == 0:
@@ -55,15 +56,34 @@ def test_single_request_matches_oracle():
     assert abs(logdet - ldo) <= 1e-5 * abs(ldo), (logdet, ldo)
 
 
-def test_alone_equals_in_mix_bitwise():
+def test_single_request_nystrom():
+    # The same request solved with the Nyström preconditioner (128 landmarks):
+    # fewer CG iterations, the same accuracy, and the SLQ log-determinant of
+    # the Jacobi run (the Lanczos columns do not depend on the CG column).
+    X, y, Z = _req(3000, 3, 1)
+    srv = Server(hbm_budget=8 << 30, max_active=8)
+    (xj, ldj, itj, _, _), = _run(srv, [(X, y, Z)])
+    (x, logdet, iters, relres, conv), = _run(srv, [(X, y, Z)], precond_rank=128)
+    srv.close()
+    print("serving CG iterations: Jacobi %d, Nyström %d" % (itj, iters))
+    assert conv and relres <= 1e-6 and iters < itj / 2
+    K = oracle.khat_dense(X, 0, 0.2, 1.0, 1e-2)
+    tr = np.linalg.norm(y - K @ x.astype(np.float64)) / np.linalg.norm(y)
+    floor = 6e-8 * np.linalg.norm(np.abs(K) @ np.abs(x.astype(np.float64))) / np.linalg.norm(y)
+    assert tr <= 1e-6 + 50 * floor, (tr, floor)
+    assert logdet == pytest.approx(ldj, rel=1e-12)
+
+
+@pytest.mark.parametrize("rank", [0, 96])
+def test_alone_equals_in_mix_bitwise(rank):
     target = _req(2500, 3, 2)
     others = [_req(n, d, 10 + i) for i, (n, d) in enumerate([(1200, 2), (4000, 8), (900, 3),
                                                             (3300, 2), (1800, 8)])]
     s1 = Server(hbm_budget=8 << 30, max_active=8)
-    alone = _run(s1, [target])[0]
+    alone = _run(s1, [target], precond_rank=rank)[0]
     s1.close()
     s2 = Server(hbm_budget=8 << 30, max_active=8)
-    mixed = _run(s2, others[:3] + [target] + others[3:])
+    mixed = _run(s2, others[:3] + [target] + others[3:], precond_rank=rank)
     s2.close()
     mix = mixed[3]
     assert np.array_equal(alone[0], mix[0])
