@@ -7,7 +7,9 @@
 //              one maximises the squared distance to the nearest landmark,
 //              lowest index on ties; distances in FP64);
 //   M          s·I + f²·K_nr·(K_rr + εI)⁻¹·K_rn, ε = 1e-8 (keeps K_rr
-//              invertible when landmarks sit closer than the length-scale);
+//              invertible when landmarks sit closer than the length-scale;
+//              K_rr is evaluated in FP64, and ε grows ×100 up to 1e-2 only if
+//              the factorisation still fails);
 //   factor     K_rr + εI = RRᵀ (Cholesky), L = K_nr·R⁻ᵀ, so M = s·I + f²·LLᵀ;
 //   M⁻¹R       (R − L·C⁻¹·LᵀR)/s,  C = (s/f²)·I + LᵀL  (Woodbury; the
 //              eigenvalues of C are ≥ s/f², so C is well conditioned even
@@ -182,15 +184,24 @@ __global__ void nys_gram_finish(int r, int S, const double* __restrict__ part, d
   }
 }
 
-// Krr[a][b] = W[sel[a]][b] (FP64): the landmark block of K_nr.
-template <typename T>
-__global__ void nys_gather_krr(int r, const T* __restrict__ W, const int* __restrict__ sel,
-                               double* __restrict__ Krr) {
+// Krr[a][b] = k(x_sel[a], x_sel[b]) evaluated in FP64 from the (possibly
+// FP32) coordinates, so that its Cholesky factor is not spoiled by the FP32
+// rounding of K_nr; xs is the FP64 coordinate scale.
+template <typename T, int KERN>
+__global__ void nys_krr_f64(int r, int d, const T* __restrict__ X, const int* __restrict__ sel,
+                            double xs, double* __restrict__ Krr) {
   const int64_t total = (int64_t)r * r;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int a = (int)(e / r), b = (int)(e % r);
-    Krr[e] = (double)W[(int64_t)sel[a] * r + b];
+    const int64_t pa = sel[e / r], pb = sel[e % r];
+    double r2 = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double df = ((double)X[pa * d + c] - (double)X[pb * d + c]) * xs;
+      r2 = fma(df, df, r2);
+    }
+    double kv, kg;
+    kval_f64<KERN, false>(r2, kv, kg);
+    Krr[e] = kv;
   }
 }
 
@@ -494,16 +505,28 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
     hipLaunchKernelGGL((nys_kernel_matrix<T, HIGP_MATERN32>), dim3(grid_for(n * r)), dim3(256),
                        0, st, n, r, p.d, X, (const int*)P->sel, xs, Knr);
   // K_rr + εI = RRᵀ on the host, R⁻¹ back to the device.
-  hipLaunchKernelGGL((nys_gather_krr<T>), dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, r,
-                     (const T*)Knr, (const int*)P->sel, RR);
+  const double xs64 = coord_scale(p.kernel, HIGP_FP64, p.l);
+  if (p.kernel == HIGP_GAUSSIAN)
+    hipLaunchKernelGGL((nys_krr_f64<T, HIGP_GAUSSIAN>), dim3(grid_for((int64_t)r * r)), dim3(256),
+                       0, st, r, p.d, X, (const int*)P->sel, xs64, RR);
+  else
+    hipLaunchKernelGGL((nys_krr_f64<T, HIGP_MATERN32>), dim3(grid_for((int64_t)r * r)), dim3(256),
+                       0, st, r, p.d, X, (const int*)P->sel, xs64, RR);
   if (hipGetLastError() != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "preconditioner build launch failed"));
   std::vector<double> A((size_t)r * r), F, Mt;
   if (hipMemcpyAsync(A.data(), RR, A.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(set_error(HIGP_ERR_HIP, "copy of the landmark block failed"));
-  for (int a = 0; a < r; ++a) A[(size_t)a * r + a] += kNysJitter;
-  if (!chol_lower(A, r, F))
+  // ε = 1e-8; should rounding still leave K_rr + εI indefinite (landmarks
+  // that coincide), ε grows by 100× up to 1e-2.
+  bool ok = false;
+  for (double eps = kNysJitter; !ok && eps <= 1e-2 * 1.0001; eps *= 100.0) {
+    std::vector<double> Aj = A;
+    for (int a = 0; a < r; ++a) Aj[(size_t)a * r + a] += eps;
+    ok = chol_lower(Aj, r, F);
+  }
+  if (!ok)
     return fail(set_error(HIGP_ERR_INVALID_ARG, "landmark kernel block is not positive definite"));
   tri_inverse_t(F, r, Mt);
   for (int a = 0; a < r; ++a)  // R⁻¹[a][b] = Mt[b][a] (lower triangular)
