@@ -90,7 +90,7 @@ def main():
                     help="comma list of extra legs (fp64, bf16, grad, train, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
-    ap.add_argument("--serve-rank", type=int, default=256,
+    ap.add_argument("--serve-rank", type=int, default=512,
                     help="Nyström rank of the second serving replay")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
                     help="time only this form's MatVec on the n=500,000 d=8 mixture "

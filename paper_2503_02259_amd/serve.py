@@ -85,7 +85,8 @@ def footprint(n, d, nprobe, nsteps, precond_rank=0):
 def replay(requests, server, upload, tol=1e-6, max_iter=1000, nsteps=40, time_scale=1.0,
            on_done=None, precond_rank=0):
     """Open-loop replay: request i is submitted once the wall clock passes its
-    arrival time (× time_scale).  ``upload(req)`` returns the device tensors
+    arrival time (× time_scale).  ``precond_rank`` is a rank or a function of
+    the request giving one (0 = Jacobi).  ``upload(req)`` returns the device tensors
     (X, y, Z) of a request (done at arrival, outside the server).  Returns a
     dict of latencies (s), completion times and summary statistics."""
     n_req = len(requests)
@@ -98,8 +99,9 @@ def replay(requests, server, upload, tol=1e-6, max_iter=1000, nsteps=40, time_sc
         while nxt < n_req and requests[nxt].arrival * time_scale <= now:
             r = requests[nxt]
             X, y, Z = upload(r)
+            rank = precond_rank(r) if callable(precond_rank) else precond_rank
             ids[server.submit(X, y, Z, l=r.l, tol=tol, max_iter=max_iter, nsteps=nsteps,
-                              precond_rank=precond_rank)] = nxt
+                              precond_rank=rank)] = nxt
             nxt += 1
         na, nq = server.step() if ids else (0, 0)
         now = time.perf_counter() - t0
