@@ -51,7 +51,8 @@ extern "C" {
 #define HIGP_ERR_OOM (-3)         /* device scratch allocation failed */
 #define HIGP_ERR_HIP (-4)         /* a HIP runtime call failed (message has the detail) */
 
-#define HIGP_MAX_D 8  /* largest point dimension d */
+#define HIGP_MAX_D 32 /* largest point dimension d (the BF16 forms and the
+                         server take d ≤ 8; the paper's on-the-fly runs use 20) */
 #define HIGP_MAX_K 64 /* largest number of vectors k per call */
 
 typedef enum { HIGP_GAUSSIAN = 0, HIGP_MATERN32 = 1 } higp_kernel;
@@ -249,9 +250,10 @@ int higp_fps_landmarks(const higp_problem* p, int32_t rank, int32_t* idx, void* 
 typedef struct {
   double tol;        /* PCG tolerance of the solves with K̂ (> 0) */
   int32_t max_iter;  /* PCG cap per solve (≥ 1; the paper's prediction runs use 50) */
-  int32_t precond;   /* 0 = none, 1 = Jacobi, 2 = Nyström with min(n, 1024) landmarks */
+  int32_t precond;   /* 0 = none, 1 = Jacobi, 2 = Nyström */
   int32_t want_var;  /* 1: also the latent predictive variance; 0: mean only */
-  int32_t reserved;  /* must be 0 */
+  int32_t rank;      /* Nyström landmarks, 0..2048 (0: min(n, 1024)); must be 0 unless
+                        precond is 2 (the paper's prediction runs use rank 100) */
 } higp_predict_opts;
 
 /* GP regression prediction (`gpr_prediction` in Listing 1), the textbook GP

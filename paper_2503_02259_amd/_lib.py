@@ -62,7 +62,7 @@ class NlmlOpts(ctypes.Structure):
 class PredictOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("want_var", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("rank", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):

@@ -241,11 +241,12 @@ def kmatvec_cross(Xq, X, V, kernel, l, f, precision=None, out=None, stream=None)
 
 
 def gpr_predict(X, y, Xq, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jacobi",
-                want_var=False, precision=None, stream=None):
+                want_var=False, precision=None, stream=None, rank=0):
     """GP regression prediction at the query points Xq with the trained
     (l, f, s): returns (mean, var, info) — var is the latent predictive
     variance (None unless want_var) and info holds the iterations of the
-    α = K̂⁻¹y solve."""
+    α = K̂⁻¹y solve.  rank: Nyström landmarks when precond is "nystrom"
+    (0: min(n, 1024))."""
     p = problem(X, kernel, l, f, s, precision)
     m = Xq.shape[0]
     if Xq.dim() != 2 or Xq.shape[1] != p.d:
@@ -255,7 +256,7 @@ def gpr_predict(X, y, Xq, kernel, l, f, s, tol=1e-6, max_iter=1000, precond="jac
     mean = torch.empty(m, dtype=X.dtype, device=X.device)
     var = torch.empty(m, dtype=X.dtype, device=X.device) if want_var else None
     o = _lib.PredictOpts(tol=float(tol), max_iter=int(max_iter), precond=_PRECOND[precond],
-                         want_var=1 if want_var else 0, reserved=0)
+                         want_var=1 if want_var else 0, rank=int(rank))
     its = ctypes.c_int32()
     _lib.check(_lib.lib().higp_gpr_predict(
         ctypes.byref(p), yp, m, xq, ctypes.byref(o), ctypes.c_void_p(mean.data_ptr()),

@@ -296,7 +296,7 @@ int higp_gpr_predict(const higp_problem* hp, const void* y, int64_t m, const voi
     return set_error(HIGP_ERR_INVALID_ARG, "y, Xq, opts and mean must be non-NULL");
   if (!(o->tol > 0.0) || o->max_iter < 1 || o->precond < 0 || o->precond > 2 ||
       (o->precond == 2 && !(p.s > 0.0)) || (o->want_var != 0 && o->want_var != 1) ||
-      o->reserved != 0)
+      o->rank < 0 || o->rank > 2048 || (o->rank != 0 && o->precond != 2))
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
   if ((o->want_var != 0) != (var != nullptr))
     return set_error(HIGP_ERR_INVALID_ARG, "var must be non-NULL exactly when want_var is 1");

@@ -329,6 +329,7 @@ int launch_kmatvec_bf16(const Problem& p, int k, const void* Vin, MatvecOut out,
                         int num_cus, bool split) {
   if (out.dl || out.df)
     return set_error(HIGP_ERR_UNSUPPORTED, "derivative MatVecs are not provided in the BF16 forms");
+  if (p.d > 8) return set_error(HIGP_ERR_UNSUPPORTED, "the BF16 forms take d <= 8");
   const int da = ((p.d + 2) + 1) / 2 * 2;  // augmented length, even
   const int nb = k <= 32 ? 1 : 2;
   Fn fn = p.kernel == HIGP_GAUSSIAN ? pick<HIGP_GAUSSIAN>(da, nb, split)

@@ -28,8 +28,8 @@
 // into FP64 running totals, so a long FP32 accumulation over n terms does
 // not build up rounding error.
 //
-// Points come from a prepared copy Xp (step a1): x̃ padded to P = 4 or 8
-// floats with zeros, and padded to whole J tiles with far-away sentinel
+// Points come from a prepared copy Xp (step a1): x̃ padded to P = 4, 8, 16,
+// 20 or 32 floats with zeros, and padded to whole J tiles with far-away sentinel
 // points (all coordinates kFar) whose kernel value is exactly 0, so no tile
 // needs masking in the inner loop.  V is read as a contiguous block of 128·k
 // floats per tile (row stride k in LDS); reads past its end return 0.
@@ -76,10 +76,15 @@ Fn pick_cols(int k, int* rb) {
 
 template <int KERN, bool GRAD>
 Fn pick_d(int d, int k, int* rb) {
-  if (d <= 2) return pick_cols<KERN, 2, GRAD>(k, rb);
-  if (d == 3) return pick_cols<KERN, 3, GRAD>(k, rb);
-  if (d == 4) return pick_cols<KERN, 4, GRAD>(k, rb);
-  return pick_cols<KERN, 8, GRAD>(k, rb);
+  switch (dim_code(d)) {
+    case 2: return pick_cols<KERN, 2, GRAD>(k, rb);
+    case 3: return pick_cols<KERN, 3, GRAD>(k, rb);
+    case 4: return pick_cols<KERN, 4, GRAD>(k, rb);
+    case 8: return pick_cols<KERN, 8, GRAD>(k, rb);
+    case 16: return pick_cols<KERN, 16, GRAD>(k, rb);
+    case 20: return pick_cols<KERN, 20, GRAD>(k, rb);
+    default: return pick_cols<KERN, 32, GRAD>(k, rb);
+  }
 }
 
 // Split count override for tuning experiments (HIGP_F32_SPLITS; 0 = automatic).
@@ -125,7 +130,7 @@ static int run_f32(const Problem& p, int64_t m, const float* Xq, int k, const vo
   const double cl = p.f * p.f * dl_factor(p.kernel, HIGP_FP32, p.l);
 
   const int bm = 32 * rb * kWaves;
-  const int P = p.d <= 4 ? 4 : 8;
+  const int P = pad_dim(dim_code(p.d));
   const int64_t nk = p.n * k;   // V elements
   const int64_t mk = rows * k;  // Y elements
   const int64_t jt_count = (p.n + kBJ - 1) / kBJ;
@@ -177,20 +182,12 @@ static int run_f32(const Problem& p, int64_t m, const float* Xq, int k, const vo
   }
   {
     const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
-    if (P == 4)
-      hipLaunchKernelGGL(prep_points_f32<4>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
-                         static_cast<const float*>(p.X), xs, Xp);
-    else
-      hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
-                         static_cast<const float*>(p.X), xs, Xp);
+    hipLaunchKernelGGL(prep_points_f32, dim3(pb), dim3(256), 0, st, p.n, npad, p.d, P,
+                       static_cast<const float*>(p.X), xs, Xp);
     if (cross) {
       const unsigned qb = (unsigned)std::min<int64_t>((mpad * P + 255) / 256, 4096);
-      if (P == 4)
-        hipLaunchKernelGGL(prep_points_f32<4>, dim3(qb), dim3(256), 0, st, m, mpad, p.d, Xq, xs,
-                           Xqp);
-      else
-        hipLaunchKernelGGL(prep_points_f32<8>, dim3(qb), dim3(256), 0, st, m, mpad, p.d, Xq, xs,
-                           Xqp);
+      hipLaunchKernelGGL(prep_points_f32, dim3(qb), dim3(256), 0, st, m, mpad, p.d, P, Xq, xs,
+                         Xqp);
     }
   }
   Args a{};

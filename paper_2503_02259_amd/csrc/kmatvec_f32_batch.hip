@@ -96,20 +96,16 @@ int batch_splits(int64_t n) {
 
 size_t prepared_points_bytes(int64_t n, int d) {
   const int64_t npad = (n + kBJ - 1) / kBJ * kBJ;
-  return (size_t)npad * (d <= 4 ? 4 : 8) * 4;
+  return (size_t)npad * pad_dim(dim_code(d)) * 4;
 }
 
 int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st) {
-  const int P = p.d <= 4 ? 4 : 8;
+  const int P = pad_dim(dim_code(p.d));
   const int64_t npad = (p.n + kBJ - 1) / kBJ * kBJ;
   const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
   const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
-  if (P == 4)
-    hipLaunchKernelGGL(prep_points_f32<4>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
-                       static_cast<const float*>(p.X), xs, Xp);
-  else
-    hipLaunchKernelGGL(prep_points_f32<8>, dim3(pb), dim3(256), 0, st, p.n, npad, p.d,
-                       static_cast<const float*>(p.X), xs, Xp);
+  hipLaunchKernelGGL(prep_points_f32, dim3(pb), dim3(256), 0, st, p.n, npad, p.d, P,
+                     static_cast<const float*>(p.X), xs, Xp);
   return hipGetLastError() == hipSuccess ? HIGP_OK : set_error(HIGP_ERR_HIP, "prep launch failed");
 }
 

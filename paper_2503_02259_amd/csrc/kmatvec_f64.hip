@@ -44,7 +44,7 @@ constexpr int kBJ64 = 64;  // J points per LDS tile (FP64 kernel)
 
 template <int KERN, int D, int NB, bool GRAD>
 __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
-  constexpr int P = D <= 4 ? 4 : 8;
+  constexpr int P = D <= 4 ? 4 : (D <= 8 ? 8 : (D + 3) / 4 * 4);
   constexpr int VC = NB * 16;
   constexpr int BM = 16 * kWaves;
   __shared__ double Xs[2][kBJ64][P];
@@ -224,7 +224,10 @@ KFn<double> pick_f64_d(int d, int k) {
   if (d <= 2) return pick_f64_cols<KERN, 2, GRAD>(k);
   if (d == 3) return pick_f64_cols<KERN, 3, GRAD>(k);
   if (d == 4) return pick_f64_cols<KERN, 4, GRAD>(k);
-  return pick_f64_cols<KERN, 8, GRAD>(k);
+  if (d <= 8) return pick_f64_cols<KERN, 8, GRAD>(k);
+  if (d <= 16) return pick_f64_cols<KERN, 16, GRAD>(k);
+  if (d <= 20) return pick_f64_cols<KERN, 20, GRAD>(k);
+  return pick_f64_cols<KERN, 32, GRAD>(k);
 }
 
 // Number of J splits S (a power of two ≤ 64) so that the grid has at least

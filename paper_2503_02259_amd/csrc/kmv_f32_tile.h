@@ -16,9 +16,19 @@ constexpr float kFar = 1e18f;  // squared distance ~1e36: exp2 underflows to exa
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Padded storage width of a point with D coordinates: 4, 8, or D rounded up
+// to a multiple of 4 (16-byte loads).
+__host__ __device__ constexpr int pad_dim(int d) {
+  return d <= 4 ? 4 : (d <= 8 ? 8 : (d + 3) / 4 * 4);
+}
+
+// Compile-time dimension of the kernel instance serving d coordinates.
+inline int dim_code(int d) {
+  return d <= 2 ? 2 : d == 3 ? 3 : d == 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 20 ? 20 : 32;
+}
+
 // a1: x̃ = x·xs padded to P floats; rows n..npad−1 are far-away sentinels.
-template <int P>
-__global__ void prep_points_f32(int64_t n, int64_t npad, int d, const float* __restrict__ X,
+__global__ void prep_points_f32(int64_t n, int64_t npad, int d, int P, const float* __restrict__ X,
                                 float xs, float* __restrict__ Xp) {
   const int64_t count = npad * P;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -61,7 +71,7 @@ struct Args {
 // written to part[split].  Called by every thread of a 256-thread workgroup.
 template <int KERN, int D, int NB, int NV, int RB, bool GRAD, bool EXACT>
 __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int split, float* smem) {
-  constexpr int P = D <= 4 ? 4 : 8;
+  constexpr int P = pad_dim(D);
   constexpr int BM = 32 * RB * kWaves;
   constexpr int NBa = NB > 0 ? NB : 1;
   constexpr int NVa = NV > 0 ? NV : 1;
@@ -187,23 +197,16 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
     for (int st = 0; st < kBJ / 2; ++st) {
       const float* xj = xs + st * 2 * P;
       float kv[RB], kg[RB];
+      f32x4 xv[P / 4];  // x_j, shared by the RB rows
+#pragma unroll
+      for (int q = 0; q < P / 4; ++q) xv[q] = *reinterpret_cast<const f32x4*>(xj + 4 * q);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         float r2 = 0.0f;
-        const f32x4 xa = *reinterpret_cast<const f32x4*>(xj);
-        if constexpr (P == 4) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) {
-            const float df = xi[rb][c] - xa[c];
-            r2 = fmaf(df, df, r2);
-          }
-        } else {
-          const f32x4 xb = *reinterpret_cast<const f32x4*>(xj + 4);
-#pragma unroll
-          for (int c = 0; c < D; ++c) {
-            const float df = xi[rb][c] - (c < 4 ? xa[c & 3] : xb[c & 3]);
-            r2 = fmaf(df, df, r2);
-          }
+        for (int c = 0; c < D; ++c) {
+          const float df = xi[rb][c] - xv[c >> 2][c & 3];
+          r2 = fmaf(df, df, r2);
         }
         kval_f32<KERN, GRAD>(r2, kv[rb], kg[rb]);
       }

@@ -61,6 +61,7 @@ int predict_impl(const Problem& p, const void* y, int64_t m, const void* Xq,
   po.tol = o.tol;
   po.max_iter = o.max_iter;
   po.precond = o.precond;
+  po.rank = o.rank;
   po.refine_prec = HIGP_FP64;
   std::vector<int32_t> it(kVarBlock);
   std::vector<double> rel(kVarBlock);

@@ -467,6 +467,7 @@ int higp_server_submit(higp_server* h, const higp_request* rq, int64_t* id) {
   HIGP_TRY(validate_problem(&rq->p, &p));
   if (p.prec != HIGP_FP32)
     return set_error(HIGP_ERR_UNSUPPORTED, "the server runs the FP32 form");
+  if (p.d > 8) return set_error(HIGP_ERR_UNSUPPORTED, "the server takes d <= 8");
   if (!rq->y || !rq->x_out) return set_error(HIGP_ERR_INVALID_ARG, "y and x_out must be non-NULL");
   if (rq->nprobe < 0 || rq->nprobe > 31 || (rq->nprobe > 0 && (!rq->Z || rq->nsteps < 1 ||
                                                                rq->nsteps > 1024)))

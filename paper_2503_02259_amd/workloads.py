@@ -120,6 +120,23 @@ def workload_grad(n=200_000):
     return Problem(X, GAUSSIAN, 0.2, 1.0, 0.05, dict(y=y, Z=Z, fd_h=1e-4))
 
 
+def workload_paper_shape(n=30_000, m=3_000, d=20):
+    """The shape of the paper's on-the-fly runs (n = 30,000 training points
+    in d = 20; "Numerical Experiments"), as synthetic data standing in for
+    its 20-D test-function data sets: points uniform in [0,1]^d, target
+    sin(2π x₀) + Σ_c x_c/d + N(0, 0.1²), and like the paper, features and
+    targets z-scored with the training set's statistics.  Returns
+    (X_train, y_train, X_test, y_test)."""
+    g = rng(6, 0)
+    Xa = g.random((n + m, d))
+    ya = np.sin(2.0 * np.pi * Xa[:, 0]) + Xa.mean(axis=1) + 0.1 * rng(6, 1).standard_normal(n + m)
+    mu, sd = Xa[:n].mean(axis=0), Xa[:n].std(axis=0)
+    Xa = (Xa - mu) / sd
+    ym, ys = ya[:n].mean(), ya[:n].std()
+    ya = (ya - ym) / ys
+    return Xa[:n], ya[:n], Xa[n:], ya[n:]
+
+
 @dataclass
 class Request:
     rid: int

@@ -38,7 +38,7 @@ def _prob(**kw):
     return p
 
 
-@pytest.mark.parametrize("field,value", [("n", 0), ("n", -5), ("d", 0), ("d", 9), ("l", 0.0),
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", -5), ("d", 0), ("d", 33), ("l", 0.0),
                                          ("l", -1.0), ("s", -1e-3), ("kernel", 7), ("prec", 5),
                                          ("reserved", 1), ("X", None), ("l", float("nan")),
                                          ("f", float("inf"))])
@@ -183,7 +183,7 @@ def test_coldot_and_nlml_reject_bad_arguments():
 def test_request_footprint_host_logic():
     L = _lib.lib()
     f = lambda n, d, N, m, r=0: int(L.higp_request_footprint(n, d, N, m, r))
-    assert f(0, 3, 16, 40) == 0 and f(100, 9, 16, 40) == 0 and f(100, 3, 32, 40) == 0
+    assert f(0, 3, 16, 40) == 0 and f(100, 33, 16, 40) == 0 and f(100, 3, 32, 40) == 0
     a, b = f(10_000, 3, 16, 40), f(20_000, 3, 16, 40)
     assert 0 < a < b
     # the Lanczos basis dominates: (m + 1)·n·N·8 bytes
@@ -213,10 +213,10 @@ def test_kmatvec_cross_validation():
 def test_gpr_predict_validation():
     L = _lib.lib()
     y, xq, mean, var = (ctypes.c_void_p(v) for v in (0x2000, 0x100000, 0x900000, 0xA00000))
-    good = dict(tol=1e-6, max_iter=50, precond=1, want_var=0, reserved=0)
+    good = dict(tol=1e-6, max_iter=50, precond=1, want_var=0, rank=0)
     p = _prob()
     for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=3), dict(want_var=2),
-                dict(reserved=1)):
+                dict(rank=100), dict(precond=2, rank=-1), dict(precond=2, rank=2049)):
         o = _lib.PredictOpts(**dict(good, **bad))
         rc = L.higp_gpr_predict(ctypes.byref(p), y, 5, xq, ctypes.byref(o), mean, None, None, None)
         assert rc == _lib.HIGP_ERR_INVALID_ARG, bad

@@ -14,9 +14,10 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
 @pytest.mark.parametrize("n,d,k", [(1, 2, 1), (257, 3, 33), (1200, 3, 17), (800, 8, 64),
-                                   (3001, 2, 2)])
+                                   (3001, 2, 2), (700, 20, 33), (400, 13, 5)])
 def test_grad_matvec_matches_oracle(n, d, k, kernel, dtype):
-    p = W.random_problem(n, d, 40 + n + k, kernel=kernel, l=0.3, f=1.1, s=0.05, k=k)
+    l = 0.3 * max(1.0, np.sqrt(d / 3.0))  # keep K away from the identity at high d
+    p = W.random_problem(n, d, 40 + n + k, kernel=kernel, l=l, f=1.1, s=0.05, k=k)
     X = as_prec(p.X, dtype)
     V = as_prec(p.extra["V"], dtype)
     outs = hg.kmatvec_grad(to_dev(X, dtype), to_dev(V, dtype), kernel, p.l, p.f, p.s)

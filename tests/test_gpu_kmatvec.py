@@ -82,3 +82,42 @@ def test_full_size_fp32_sampled_rows(kernel):
     lhs = Y.sum(0)
     rhs = (K1 * V).sum(0)
     assert np.all(np.abs(lhs - rhs) <= 1e-5 * np.abs(K1).sum() * np.abs(V).max(0))
+
+
+HIGH_D = [(700, 9, 33), (513, 12, 5), (1001, 16, 64), (300, 17, 1), (1500, 20, 33),
+          (257, 25, 17), (900, 32, 2)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
+@pytest.mark.parametrize("n,d,k", HIGH_D)
+def test_kmatvec_high_dimension_matches_oracle(n, d, k, kernel, dtype):
+    # Up to d = 32 (the paper's on-the-fly runs use d = 20).  The length-scale
+    # grows with √d so that the kernel matrix stays far from the identity.
+    seed = n * 17 + d
+    l = 0.35 * np.sqrt(d / 3.0)
+    p = W.random_problem(n, d, seed, kernel=kernel, l=l, f=1.3, s=0.05, k=k)
+    X = as_prec(p.X, dtype)
+    V = as_prec(p.extra["V"], dtype)
+    Y = hg.kmatvec(to_dev(X, dtype), to_dev(V, dtype), kernel, p.l, p.f, p.s)
+    ref = oracle.kmatvec(X, V, kernel, p.l, p.f, p.s)
+    offdiag = oracle.kmatvec(X, V, kernel, p.l, p.f, 0.0) - p.f ** 2 * V
+    assert np.linalg.norm(offdiag) > 0.1 * np.linalg.norm(ref)  # not just the diagonal
+    err = colrel(Y.cpu().numpy(), ref)
+    assert err.max() <= TOL[dtype], (err.max(), n, d, k)
+
+
+def test_bf16_and_server_reject_high_dimension():
+    p = W.random_problem(100, 12, 3, k=4)
+    X = to_dev(as_prec(p.X, torch.float32), torch.float32)
+    V = to_dev(as_prec(p.extra["V"], torch.float32), torch.float32)
+    for prec in ("bf16", "bf16x3"):
+        with pytest.raises(hg.HigpError) as e:
+            hg.kmatvec(X, V, 0, 0.5, 1.0, 0.1, precision=prec)
+        assert e.value.code == -2
+    from paper_2503_02259_amd.serve import Server
+    srv = Server(hbm_budget=1 << 30, max_active=2)
+    with pytest.raises(hg.HigpError) as e:
+        srv.submit(X, V[:, 0].contiguous())
+    assert e.value.code == -2
+    srv.close()

@@ -19,13 +19,14 @@ def _pts(n, d, seed, stream=0):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
 @pytest.mark.parametrize("m,n,d,k", [(1, 1, 1, 1), (130, 257, 3, 33), (1000, 700, 8, 5),
-                                     (64, 3000, 2, 64), (5000, 100, 3, 1), (333, 2049, 5, 17)])
+                                     (64, 3000, 2, 64), (5000, 100, 3, 1), (333, 2049, 5, 17),
+                                     (500, 1200, 20, 3)])
 def test_cross_matvec_matches_oracle(m, n, d, k, kernel, dtype):
     seed = m + n + d + k
     X = as_prec(_pts(n, d, seed), dtype)
     Xq = as_prec(_pts(m, d, seed, 1), dtype)
     V = as_prec(W.rng(600 + seed, 4).standard_normal((n, k)), dtype)
-    l, f = 0.3, 1.2
+    l, f = 0.3 * max(1.0, np.sqrt(d / 3.0)), 1.2
     Y = hg.kmatvec_cross(to_dev(Xq, dtype), to_dev(X, dtype), to_dev(V, dtype), kernel, l, f)
     ref = oracle.kmatvec_cross(Xq, X, V, kernel, l, f, workers=8)
     err = colrel(Y.cpu().numpy(), ref).max()
@@ -77,6 +78,24 @@ def test_prediction_fp32_matches_oracle():
     ev = np.abs(var.cpu().numpy() - rv).max()
     print("FP32 prediction: mean %.2e, var %.2e (abs)" % (em, ev))
     assert em <= 1e-3 and ev <= 1e-3
+
+
+@pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
+def test_prediction_nystrom_rank100_d20_matches_oracle(kernel):
+    # The paper's prediction setting in small: d = 20 z-scored points, a
+    # rank-100 preconditioner; FP64 and solved to 1e-11, so the mean must
+    # agree with the dense posterior whatever the preconditioner is.
+    Xtr, ytr, Xte, _ = W.workload_paper_shape(n=1500, m=200)
+    l, f, s = 3.0, 1.0, 0.05
+    mean, var, info = hg.gpr_predict(to_dev(Xtr, torch.float64), to_dev(ytr, torch.float64),
+                                     to_dev(Xte, torch.float64), kernel, l, f, s, tol=1e-11,
+                                     max_iter=2000, precond="nystrom", rank=100, want_var=True)
+    rm, rv = oracle.gpr_predict(Xtr, ytr, Xte, kernel, l, f, s)
+    em = np.linalg.norm(mean.cpu().numpy() - rm) / np.linalg.norm(rm)
+    ev = np.abs(var.cpu().numpy() - rv).max()
+    print("Nyström-100 d=20 prediction: mean %.2e, var %.2e, α iterations %d"
+          % (em, ev, info["pcg_iters"]))
+    assert em <= 1e-8 and ev <= 1e-8
 
 
 def test_prediction_far_queries_give_the_prior():
