@@ -109,7 +109,8 @@ class GPRModel(torch.nn.Module):
         return float(loss.detach())
 
     def get_params(self):
-        l, f, s = self.theta()
+        with torch.no_grad():
+            l, f, s = self.theta()
         return dict(l=float(l), f=float(f), s=float(s))
 
 
