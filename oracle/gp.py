@@ -85,3 +85,57 @@ def nlml_grad_hutchinson(X, y, Z, kernel, l, f, s, jacobi=True):
         hutch = float(np.mean(np.sum(W * GA[:, 1:], axis=0) - corr))
         out.append(0.5 * (-quad + tr_m + hutch))
     return np.array(out)
+
+
+def orth_range(Y, rcond=1e-7):
+    """Orthonormal basis of the range of Y (n×s): the left singular vectors
+    whose singular values exceed rcond·σ_max (a rank-revealing orth, as
+    Hutch++ needs when AS is rank-deficient)."""
+    U, sv, _ = np.linalg.svd(np.asarray(Y, dtype=np.float64), full_matrices=False)
+    if sv.size == 0 or sv[0] == 0.0:
+        return U[:, :0]
+    return U[:, sv > rcond * sv[0]]
+
+
+def hutchpp_trace(apply_a, S, G, rcond=1e-7):
+    """Hutch++ (Meyer, Musco, Musco & Woodruff 2021, the estimator the paper
+    cites next to Hutchinson's for eq. (2)): with sketch probes S and
+    Hutchinson probes G, Q = orth(A·S) and
+        tr(A) ≈ tr(QᵀAQ) + (1/|G|)·tr(Gᵀ(I − QQᵀ)A(I − QQᵀ)G).
+    apply_a(V) -> A·V for an n×k block."""
+    S = np.asarray(S, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    Q = orth_range(apply_a(S), rcond)
+    top = float(np.trace(Q.T @ apply_a(Q))) if Q.shape[1] else 0.0
+    Gp = G - Q @ (Q.T @ G)
+    rest = float(np.trace(Gp.T @ apply_a(Gp))) / G.shape[1]
+    return top + rest
+
+
+def nlml_grad_hutchpp(X, y, Z, kernel, l, f, s, jacobi=True, rcond=1e-7):
+    """(∂L/∂l, ∂L/∂f, ∂L/∂s) with the second term of eq. (2),
+    tr(K̂⁻¹∂K̂/∂θ − M⁻¹∂M/∂θ), estimated by Hutch++ per θ (``hutchpp_trace``)
+    instead of Hutchinson's estimator.  The probe block Z (n×N) is split into
+    the sketch S = Z[:, :N//2] and the Hutchinson probes G = Z[:, N//2:]
+    (Meyer et al. give the sketch and the remainder equal shares).  M is
+    diag(K̂) = (f²+s)·I with ``jacobi``, else I.  Solves are exact (dense
+    Cholesky), so this is the estimator's value for the given probes."""
+    y = np.asarray(y, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    n, N = Z.shape
+    ns = N // 2
+    S, G = Z[:, :ns], Z[:, ns:]
+    cf = scipy.linalg.cho_factor(khat_dense(X, kernel, l, f, s), lower=True)
+    alpha = scipy.linalg.cho_solve(cf, y)
+    D = _dkhat(X, kernel, l, f, s)
+    m = f * f + s
+    cm = {"l": 0.0, "f": 2.0 * f / m, "s": 1.0 / m} if jacobi else {"l": 0.0, "f": 0.0, "s": 0.0}
+    out = []
+    for t in ("l", "f", "s"):
+        c = cm[t]
+
+        def apply_a(V, Dt=D[t], c=c):
+            return scipy.linalg.cho_solve(cf, Dt @ V) - c * V
+        est = hutchpp_trace(apply_a, S, G, rcond)
+        out.append(0.5 * (-float(alpha @ (D[t] @ alpha)) + c * n + est))
+    return np.array(out)

@@ -12,19 +12,25 @@ Test infrastructure only (see ``oracle/__init__``).
   the stochastic Lanczos quadrature of Ubaru et al. (2017): Lanczos from
   z/‖z‖, eigen-decomposition T = S Θ Sᵀ, and ‖z‖² Σ_k S_{1k}² log θ_k per
   probe, averaged over probes.
+* The same quadrature can take its tridiagonal from the coefficients of a
+  PCG run on the probe (the CG–Lanczos correspondence, Saad 2003 §6.7.3;
+  GPyTorch's mBCG, Gardner et al. 2018): no separate Lanczos pass.
 """
 import numpy as np
 import scipy.linalg
 
 
 def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
-        true_matvec=None, apply_minv=None):
+        true_matvec=None, apply_minv=None, coeffs=None):
     """Solve A X = B column by column with (Jacobi-)preconditioned CG.
 
     matvec(P) -> A·P for an n×k block.  mdiag: diagonal of M (None = no
-    preconditioner); apply_minv(R) -> M⁻¹R for a general SPD M instead.  refine_every = R > 0 replaces the recursive residual by
-    the true residual b − A·x (computed with ``true_matvec``, default
-    ``matvec``) after every R-th iteration of a column.
+    preconditioner); apply_minv(R) -> M⁻¹R for a general SPD M instead.
+    refine_every = R > 0 replaces the recursive residual by the true residual
+    b − A·x (computed with ``true_matvec``, default ``matvec``) after every
+    R-th iteration of a column.  coeffs: a dict that receives, per column,
+    the step lengths α_j ("alpha") and the direction coefficients β_j
+    ("beta", one per iteration that is followed by another) as lists.
 
     Returns (X, iters, relres, converged) with per-column arrays; relres is the
     recursive relative residual at exit.
@@ -50,12 +56,18 @@ def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
     iters = np.zeros(k, dtype=np.int64)
     relres = np.where(bnorm > 0, np.linalg.norm(R, axis=0) / np.where(bnorm > 0, bnorm, 1.0), 0.0)
     active = relres > tol
+    if coeffs is not None:
+        coeffs["alpha"] = [[] for _ in range(k)]
+        coeffs["beta"] = [[] for _ in range(k)]
     for _ in range(max_iter):
         if not active.any():
             break
         Q = matvec(P)
         a = active
         alpha = rho[a] / np.sum(P[:, a] * Q[:, a], axis=0)
+        if coeffs is not None:
+            for c, v in zip(np.flatnonzero(a), alpha):
+                coeffs["alpha"][c].append(float(v))
         X[:, a] += alpha * P[:, a]
         R[:, a] -= alpha * Q[:, a]
         iters[a] += 1
@@ -66,12 +78,15 @@ def pcg(matvec, B, tol, max_iter, mdiag=None, x0=None, refine_every=0,
         relres[a] = np.linalg.norm(R[:, a], axis=0) / bnorm[a]
         done = a & (relres <= tol)
         active = a & ~done
-        a = active
+        a = active & (iters < max_iter)
         if not a.any():
             break
         Z = prec(R)
         rho_new = np.sum(R[:, a] * Z[:, a], axis=0)
         beta = rho_new / rho[a]
+        if coeffs is not None:
+            for c, v in zip(np.flatnonzero(a), beta):
+                coeffs["beta"][c].append(float(v))
         rho[a] = rho_new
         P[:, a] = Z[:, a] + beta * P[:, a]
     converged = relres <= tol
@@ -176,3 +191,48 @@ def slq_logdet(matvec, Z, m, reorth=True, mdiag=None):
     per = np.array([logm + slq_from_tridiag(a, b, zn2[c])
                     for c, (a, b) in enumerate(zip(alphas, betas))])
     return float(np.mean(per)), per
+
+
+def tridiag_from_cg(alpha, beta):
+    """The Lanczos tridiagonal that m PCG steps implicitly build (Saad 2003,
+    §6.7.3), from their step lengths α_0..α_{m−1} and direction
+    coefficients β_0..β_{m−2}:
+        T_00 = 1/α_0,   T_jj = 1/α_j + β_{j−1}/α_{j−1} (j ≥ 1),
+        T_{j,j+1} = T_{j+1,j} = √β_j / α_j.
+    It is the Lanczos matrix of M^{-1/2}AM^{-1/2} from M^{-1/2}b/‖M^{-1/2}b‖
+    (M = I without preconditioning), up to the signs of its off-diagonal,
+    which the quadrature does not see.  Returns (diagonal, off-diagonal)."""
+    a = np.asarray(alpha, dtype=np.float64)
+    b = np.asarray(beta, dtype=np.float64)
+    m = a.size
+    diag = 1.0 / a
+    diag[1:] += b[:m - 1] / a[:m - 1]
+    off = np.sqrt(b[:m - 1]) / a[:m - 1]
+    return diag, off
+
+
+def cg_logdet(matvec, Z, tol, max_iter, mdiag=None):
+    """Estimate log|A| by eq. (1) with M = I (mdiag None) or a constant
+    M = c·I (the Jacobi preconditioner of a stationary kernel), with the
+    stochastic Lanczos quadrature whose tridiagonals come from PCG on the
+    probe columns of Z (each column runs until its own stopping test or
+    max_iter, see ``pcg``).  PCG with M = c·I takes the steps of CG on A/c,
+    so T (``tridiag_from_cg``) is the Lanczos matrix of A/c from z/‖z‖ and
+    the probe value is log|M| + ‖z‖²·e₁ᵀlog(T)e₁, as in ``slq_logdet``.
+    Returns (logdet, per_probe, iters)."""
+    Z = np.asarray(Z, dtype=np.float64)
+    if Z.ndim == 1:
+        Z = Z[:, None]
+    if mdiag is not None:
+        md = np.asarray(mdiag, dtype=np.float64)
+        assert np.all(md == md[0]), "cg_logdet takes M = I or a constant diagonal"
+    coeffs = {}
+    _, iters, _, _ = pcg(matvec, Z, tol, max_iter, mdiag=mdiag, coeffs=coeffs)
+    logm = 0.0 if mdiag is None else float(np.sum(np.log(np.asarray(mdiag, dtype=np.float64))))
+    zn2 = np.sum(Z * Z, axis=0)
+    per = []
+    for c in range(Z.shape[1]):
+        diag, off = tridiag_from_cg(coeffs["alpha"][c], coeffs["beta"][c])
+        per.append(logm + slq_from_tridiag(diag, off, zn2[c]))
+    per = np.array(per)
+    return float(np.mean(per)), per, iters

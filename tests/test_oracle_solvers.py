@@ -154,3 +154,65 @@ def test_lanczos_reorth_agreement_between_orders():
     for c in range(2):
         np.testing.assert_allclose(a1[c], a2[c], rtol=1e-10)
         np.testing.assert_allclose(b1[c], b2[c], rtol=1e-9)
+
+
+# ---- log-determinant from the PCG coefficients (CG–Lanczos correspondence)
+
+def test_cg_tridiagonal_equals_lanczos_in_early_steps():
+    # Before orthogonality is lost, the T that PCG implicitly builds is the
+    # Lanczos T from the same start vector (Lanczos with full
+    # reorthogonalisation, pinned above against dense spectra).
+    n = 300
+    X, mv, K = _setup(n=n, seed=3, l=0.3, s=0.1)
+    Z = W.rademacher(n, 3, 21)
+    co = {}
+    oracle.pcg(mv, Z, 1e-15, 10, coeffs=co)
+    la, lb = oracle.lanczos(mv, Z, 10)
+    for c in range(3):
+        d, o = oracle.tridiag_from_cg(co["alpha"][c], co["beta"][c])
+        np.testing.assert_allclose(d, la[c], rtol=1e-11)
+        np.testing.assert_allclose(np.abs(o), lb[c], rtol=1e-10)
+    # with the constant Jacobi M the coefficients are those of CG on K̂/(f²+s)
+    co2 = {}
+    oracle.pcg(mv, Z, 1e-15, 10, mdiag=np.diag(K), coeffs=co2)
+    la2, _ = oracle.lanczos(lambda P: mv(P) / K[0, 0], Z, 10)
+    d2, _ = oracle.tridiag_from_cg(co2["alpha"][0], co2["beta"][0])
+    np.testing.assert_allclose(d2, la2[0], rtol=1e-11)
+
+
+def test_cg_logdet_to_convergence_is_the_quadratic_form():
+    # Run to convergence the quadrature is exact: ‖z‖²e₁ᵀlog(T)e₁ = zᵀlog(K̂)z.
+    n = 200
+    X, mv, K = _setup(n=n, seed=4, l=0.3, s=0.1)
+    Z = W.rademacher(n, 4, 22)
+    w, V = np.linalg.eigh(K)
+    exact = np.array([z @ (V @ (np.log(w) * (V.T @ z))) for z in Z.T])
+    for md in (None, np.diag(K)):
+        ld, per, it = oracle.cg_logdet(mv, Z, 1e-13, 500, mdiag=md)
+        assert np.all(it < 500)
+        np.testing.assert_allclose(per, exact, rtol=1e-11)
+        assert abs(ld - exact.mean()) <= 1e-11 * abs(exact.mean())
+
+
+def test_cg_logdet_large_l_closed_form():
+    # l → ∞: K̂ = f²11ᵀ + sI; CG ends after two steps and the probe value is
+    # log s·(n − (1ᵀz)²/n) + log(s + nf²)·(1ᵀz)²/n.
+    n, f, s = 64, 1.3, 0.2
+    X = W.rng(905, 0).random((n, 3))
+    mv = lambda P: oracle.kmatvec(X, P, 0, 1e8, f, s)
+    Z = W.rademacher(n, 5, 23)
+    ld, per, it = oracle.cg_logdet(mv, Z, 1e-12, 50)
+    one = Z.sum(axis=0) ** 2 / n
+    ref = np.log(s) * (n - one) + np.log(s + n * f * f) * one
+    assert np.all(it <= 2)
+    np.testing.assert_allclose(per, ref, rtol=1e-12)
+
+
+def test_cg_logdet_statistical_accuracy():
+    n = 400
+    X, mv, K = _setup(n=n, seed=7, l=0.5, s=0.01)
+    Z = W.rademacher(n, 24, 14)
+    ld, per, it = oracle.cg_logdet(mv, Z, 1e-8, 60, mdiag=np.diag(K))
+    exact = np.linalg.slogdet(K)[1]
+    se = per.std(ddof=1) / np.sqrt(per.size)
+    assert abs(ld - exact) <= 3 * se + 1e-6 * abs(exact)
