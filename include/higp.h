@@ -197,8 +197,17 @@ typedef struct {
   int32_t max_iter;     /* PCG iteration cap */
   int32_t precond;      /* 0 = none, 1 = Jacobi (also used for eq. (1) and (2)) */
   int32_t refine_every; /* PCG residual replacement period (0 = off), FP64 MatVec */
-  int32_t nsteps;       /* Lanczos steps of SLQ */
-  int32_t reorth;       /* 1 = full reorthogonalisation in SLQ */
+  int32_t nsteps;       /* Lanczos steps of SLQ (logdet_mode 0) */
+  int32_t reorth;       /* 1 = full reorthogonalisation in SLQ (logdet_mode 0) */
+  int32_t logdet_mode;  /* 0 = SLQ: a Lanczos pass over Z after the solve;
+                           1 = the tridiagonals PCG builds on the Z columns
+                           (CG–Lanczos correspondence, Saad 2003 §6.7.3, as
+                           GPyTorch's mBCG): no Lanczos pass, no
+                           reorthogonalisation; needs refine_every = 0 */
+  int32_t trace_mode;   /* 0 = Hutchinson over all of Z; 1 = Hutch++ (Meyer et
+                           al. 2021, cited with eq. (2)): sketch S = the first
+                           ⌊N/2⌋ columns of Z, Hutchinson probes G = the rest;
+                           needs 2 ≤ N ≤ 42 and logdet_mode 0 */
   int32_t reserved;     /* must be 0 */
 } higp_nlml_opts;
 

@@ -156,7 +156,12 @@ def tridiag_eig(alpha, beta):
     beta = np.asarray(beta, dtype=np.float64)
     if alpha.size == 1:
         return alpha.copy(), np.ones(1)
-    theta, S = scipy.linalg.eigh_tridiagonal(alpha, beta)
+    try:
+        theta, S = scipy.linalg.eigh_tridiagonal(alpha, beta)
+    except np.linalg.LinAlgError:
+        # LAPACK's MRRR driver can fail on long tridiagonals with clustered
+        # (ghost) eigenvalues; the implicit-QR driver does not.
+        theta, S = scipy.linalg.eigh_tridiagonal(alpha, beta, lapack_driver="stev")
     return theta, S[0, :]
 
 

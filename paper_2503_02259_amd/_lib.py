@@ -56,6 +56,7 @@ class NlmlOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("refine_every", ctypes.c_int32),
                 ("nsteps", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("logdet_mode", ctypes.c_int32), ("trace_mode", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 

@@ -199,9 +199,11 @@ def coldot(A, B, stream=None):
 
 
 def nlml(X, y, Z, kernel, l, f, s, tol=1e-6, max_iter=2000, precond="jacobi", refine_every=0,
-         nsteps=50, reorth=True, precision=None, stream=None):
+         nsteps=50, reorth=True, precision=None, stream=None, logdet="slq", trace="hutchinson"):
     """L(Θ) and (∂L/∂l, ∂L/∂f, ∂L/∂s) by PCG on [y | Z], SLQ over Z and the
-    Hutchinson estimator (eq. (1) and (2)).  Returns (loss, grad, info)."""
+    Hutchinson estimator (eq. (1) and (2)).  Returns (loss, grad, info).
+    logdet: "slq" (a Lanczos pass over Z) or "cg" (the tridiagonals of the
+    PCG run on the Z columns); trace: "hutchinson" or "hutchpp"."""
     p = problem(X, kernel, l, f, s, precision)
     n, N = Z.shape
     yp = _dev(y, "y", X.dtype, (p.n,))
@@ -209,7 +211,8 @@ def nlml(X, y, Z, kernel, l, f, s, tol=1e-6, max_iter=2000, precond="jacobi", re
     o = _lib.NlmlOpts(tol=float(tol), max_iter=int(max_iter),
                       precond={"jacobi": 1, "none": 0, None: 0, 0: 0, 1: 1}[precond],
                       refine_every=int(refine_every), nsteps=int(nsteps),
-                      reorth=1 if reorth else 0, reserved=0)
+                      reorth=1 if reorth else 0, logdet_mode={"slq": 0, "cg": 1}[logdet],
+                      trace_mode={"hutchinson": 0, "hutchpp": 1}[trace], reserved=0)
     loss = ctypes.c_double()
     logdet = ctypes.c_double()
     its = ctypes.c_int32()

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libhigp.so")
 SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f32_batch.hip", "kmatvec_f64.hip",
            "nystrom.hip",
            "kmatvec_bf16.hip", "predict.hip", "blas.hip", "pcg.hip", "slq.hip", "nlml.hip",
-           "server.hip"]
+           "hutchpp.hip", "server.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -9,8 +9,6 @@
 
 namespace higp {
 
-int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
-            higp_pcg_info* info, hipStream_t st);
 int run_slq(const Problem& p, int N, int m, const void* Z, int reorth, int precond,
             double* logdet, double* per_probe, hipStream_t st);
 int run_nlml(const Problem& p, const void* y, int N, const void* Z, const higp_nlml_opts& o,
@@ -246,8 +244,17 @@ int higp_nlml(const higp_problem* hp, const void* y, int32_t nprobe, const void*
     return set_error(HIGP_ERR_INVALID_ARG, "y, Z, opts, loss and grad must be non-NULL");
   if (!(o->tol > 0.0) || o->max_iter < 1 || (o->precond != 0 && o->precond != 1) ||
       o->refine_every < 0 || o->nsteps < 1 || o->nsteps > 1024 ||
-      (o->reorth != 0 && o->reorth != 1) || o->reserved != 0)
+      (o->reorth != 0 && o->reorth != 1) || o->logdet_mode < 0 || o->logdet_mode > 1 ||
+      o->trace_mode < 0 || o->trace_mode > 1 || o->reserved != 0)
     return set_error(HIGP_ERR_INVALID_ARG, "bad option value");
+  if (o->logdet_mode == 1 && o->refine_every != 0)
+    return set_error(HIGP_ERR_INVALID_ARG,
+                     "logdet_mode 1 reads the PCG coefficients and needs refine_every = 0");
+  if (o->logdet_mode == 1 && o->max_iter > 100000)
+    return set_error(HIGP_ERR_INVALID_ARG, "logdet_mode 1 takes max_iter ≤ 100000");
+  if (o->trace_mode == 1 && (nprobe < 2 || nprobe > 42 || o->logdet_mode != 0))
+    return set_error(HIGP_ERR_INVALID_ARG,
+                     "trace_mode 1 (Hutch++) needs 2 ≤ nprobe ≤ 42 and logdet_mode 0");
   return run_nlml(p, y, nprobe, Z, *o, loss, grad, logdet, pcg_iters,
                   static_cast<hipStream_t>(stream));
 }

@@ -104,4 +104,12 @@ int launch_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb
 int launch_cast_scale(int64_t count, const void* x, int tx, void* y, int ty, double a,
                       hipStream_t st);
 
+// PCG of higp_pcg.  With `ahist` and `bhist` (device, max_iter×k doubles,
+// row j = iteration j) the step lengths α_j and direction coefficients β_j of
+// every column are recorded as they are taken (β_j only for iterations that
+// are followed by another); only meaningful without residual replacement.
+int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
+            higp_pcg_info* info, hipStream_t st, double* ahist = nullptr,
+            double* bhist = nullptr);
+
 }  // namespace higp

@@ -1,6 +1,15 @@
 // Negative log marginal likelihood and its hand-coded gradient ("Gaussian
 // Processes": L(Θ), ∂L/∂θ, eq. (1), eq. (2), SLQ and Hutchinson), composed of
 // the library's own PCG, SLQ, derivative MatVec and column-dot kernels.
+//
+// log|K̂| comes either from SLQ (a Lanczos pass over the probes after the
+// solve) or from the tridiagonals the PCG run on [y | Z] builds implicitly for
+// the probe columns (CG–Lanczos correspondence, Saad 2003 §6.7.3; GPyTorch's
+// mBCG): with the step lengths α_j and direction coefficients β_j,
+//   T_00 = 1/α_0,  T_jj = 1/α_j + β_{j−1}/α_{j−1},  T_{j,j+1} = √β_j/α_j,
+// the Lanczos matrix of M^{-1/2}K̂M^{-1/2} from z/‖z‖ for the constant Jacobi
+// M (or M = I).  The trace term of eq. (2) uses Hutchinson's estimator here
+// and Hutch++ in hutchpp.hip.
 #include <cmath>
 #include <vector>
 
@@ -8,8 +17,30 @@
 
 namespace higp {
 
-int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
-            higp_pcg_info* info, hipStream_t st);
+int run_nlml_hutchpp(const Problem& p, const void* y, int N, const void* Z,
+                     const higp_nlml_opts& o, double* loss, double* grad, double* logdet,
+                     int32_t* iters, hipStream_t st);
+
+// Probe quadrature ‖z‖²·e₁ᵀlog(T)e₁ with T from m PCG steps (α, β host
+// arrays of m and m − 1 entries).  A zero step length (an exactly zero
+// residual) ends T there.
+int cg_quadrature(int m, const double* alpha, const double* beta, double zn2, double* out) {
+  int mm = 0;
+  while (mm < m && alpha[mm] > 0.0) ++mm;
+  if (mm < 1) return set_error(HIGP_ERR_INVALID_ARG, "a probe column has no CG step");
+  std::vector<double> a(mm), b(mm > 1 ? mm - 1 : 1), th(mm), tau(mm);
+  for (int j = 0; j < mm; ++j) {
+    a[j] = 1.0 / alpha[j];
+    if (j > 0) a[j] += beta[j - 1] / alpha[j - 1];
+    if (j + 1 < mm) b[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  HIGP_TRY(higp_tridiag_eig(mm, a.data(), b.data(), th.data(), tau.data()));
+  double q = 0.0;
+  for (int j = 0; j < mm; ++j) q += tau[j] * tau[j] * std::log(th[j]);
+  *out = zn2 * q;
+  return HIGP_OK;
+}
+
 int run_slq(const Problem& p, int N, int m, const void* Z, int reorth, int precond,
             double* logdet, double* per_probe, hipStream_t st);
 
@@ -81,9 +112,11 @@ int nlml_impl(const Problem& p, const void* y, int N, const void* Z, const higp_
     bytes += (b + 255) / 256 * 256;
     return off;
   };
+  const bool from_cg = o.logdet_mode == 1;
+  const size_t hist = from_cg ? (size_t)o.max_iter * k * 8 : 0;
   const size_t o_b = take(nk * sizeof(T)), o_x = take(nk * sizeof(T)), o_w = take(nk * 8),
                o_a = take(nk * sizeof(T)), o_dl = take(nk * sizeof(T)),
-               o_df = take(nk * sizeof(T));
+               o_df = take(nk * sizeof(T)), o_ah = take(hist), o_bh = take(hist);
   void* mem = nullptr;
   HIGP_TRY(scratch_alloc(&mem, bytes, st));
   char* base = static_cast<char*>(mem);
@@ -93,6 +126,8 @@ int nlml_impl(const Problem& p, const void* y, int N, const void* Z, const higp_
   T* A = (T*)(base + o_a);
   T* DL = (T*)(base + o_dl);
   T* DF = (T*)(base + o_df);
+  double* ahist = from_cg ? (double*)(base + o_ah) : nullptr;
+  double* bhist = from_cg ? (double*)(base + o_bh) : nullptr;
   auto done = [&](int rc) {
     (void)hipStreamSynchronize(st);
     scratch_free(mem, st);
@@ -115,15 +150,28 @@ int nlml_impl(const Problem& p, const void* y, int N, const void* Z, const higp_
   std::vector<double> rel(k);
   std::vector<int32_t> conv(k);
   higp_pcg_info info{its.data(), rel.data(), conv.data()};
-  int rc = run_pcg(p, k, B, Xs, po, &info, st);
+  int rc = run_pcg(p, k, B, Xs, po, &info, st, ahist, bhist);
   if (rc) return done(rc);
   int itmax = 0;
   for (int c = 0; c < k; ++c) itmax = its[c] > itmax ? its[c] : itmax;
 
-  // 2. log|K̂| by eq. (1) and SLQ over Z.
+  // 2. log|K̂| by eq. (1): SLQ over Z, or the PCG tridiagonals of the Z
+  //    columns (quadratures formed below, once ‖z‖² is known).
   double logdet = 0.0;
-  rc = run_slq(p, N, o.nsteps, Z, o.reorth, o.precond, &logdet, nullptr, st);
-  if (rc) return done(rc);
+  std::vector<double> ah, bh;
+  if (from_cg) {
+    ah.assign((size_t)itmax * k, 0.0);
+    bh.assign((size_t)itmax * k, 0.0);
+    if (itmax > 0 &&
+        (hipMemcpyAsync(ah.data(), ahist, ah.size() * 8, hipMemcpyDeviceToHost, st) !=
+             hipSuccess ||
+         hipMemcpyAsync(bh.data(), bhist, bh.size() * 8, hipMemcpyDeviceToHost, st) !=
+             hipSuccess))
+      return done(set_error(HIGP_ERR_HIP, "coefficient copy failed"));
+  } else {
+    rc = run_slq(p, N, o.nsteps, Z, o.reorth, o.precond, &logdet, nullptr, st);
+    if (rc) return done(rc);
+  }
 
   // 3. ∂K̂/∂θ·[α | Z] by one fused derivative MatVec.
   hipLaunchKernelGGL((pack_grad_input<T>), dim3(blocks_for(nk)), dim3(256), 0, st, n, N,
@@ -144,6 +192,22 @@ int nlml_impl(const Problem& p, const void* y, int N, const void* Z, const higp_
       (rc = host_coldot(n, k, B, tt, B, tt, bb.data(), st)))
     return done(rc);
   done(HIGP_OK);
+  if (from_cg) {
+    const double logm = o.precond ? (double)n * std::log(p.f * p.f + p.s) : 0.0;
+    std::vector<double> a(itmax), b(itmax);
+    for (int c = 1; c < k; ++c) {
+      const int m = its[c];
+      for (int j = 0; j < m; ++j) {
+        a[j] = ah[(size_t)j * k + c];
+        b[j] = bh[(size_t)j * k + c];
+      }
+      double q = 0.0;
+      rc = cg_quadrature(m, a.data(), b.data(), bb[c], &q);
+      if (rc) return rc;
+      logdet += logm + q;
+    }
+    logdet /= N;
+  }
 
   // Eq. (2) with M = diag(K̂) = (f²+s)·I: tr(M⁻¹∂M) − (1/N) Σ z_iᵀM⁻¹∂M z_i;
   // ∂M/∂l = 0, ∂M/∂f = 2f·I, ∂M/∂s = I.  Without preconditioning M = I.
@@ -173,6 +237,7 @@ int nlml_impl(const Problem& p, const void* y, int N, const void* Z, const higp_
 
 int run_nlml(const Problem& p, const void* y, int N, const void* Z, const higp_nlml_opts& o,
              double* loss, double* grad, double* logdet, int32_t* iters, hipStream_t st) {
+  if (o.trace_mode == 1) return run_nlml_hutchpp(p, y, N, Z, o, loss, grad, logdet, iters, st);
   if (p.prec == HIGP_FP64) return nlml_impl<double>(p, y, N, Z, o, loss, grad, logdet, iters, st);
   return nlml_impl<float>(p, y, N, Z, o, loss, grad, logdet, iters, st);
 }

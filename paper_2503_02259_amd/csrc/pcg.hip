@@ -34,7 +34,7 @@ namespace {
 
 template <typename T>
 int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_opts& o,
-             higp_pcg_info* info, hipStream_t st) {
+             higp_pcg_info* info, hipStream_t st, double* ahist, double* bhist) {
   const int64_t n = p.n;
   const size_t nk = (size_t)n * k;
   const RedGrid g = red_grid(n);
@@ -95,10 +95,13 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
   double* work2 = S.work + nwork;
   S.counter = (unsigned*)(base + o_cnt);
   unsigned* counter2 = S.counter + 1;
+  S.ahist = ahist;
+  S.bhist = bhist;
 
   PcgScalars ps;
   ps.tol = o.tol;
   ps.max_iter = o.max_iter;
+  ps.k = k;
   ps.minv = o.precond == 1 ? 1.0 / (p.f * p.f + p.s) : 1.0;
   ps.general_m = nys ? 1 : 0;
   // Stopping only on a replaced residual is sound when the replacement is
@@ -252,9 +255,9 @@ int pcg_impl(const Problem& p, int k, const void* Bv, void* Xv, const higp_pcg_o
 }  // namespace
 
 int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
-            higp_pcg_info* info, hipStream_t st) {
-  if (p.prec == HIGP_FP64) return pcg_impl<double>(p, k, B, X, o, info, st);
-  return pcg_impl<float>(p, k, B, X, o, info, st);
+            higp_pcg_info* info, hipStream_t st, double* ahist, double* bhist) {
+  if (p.prec == HIGP_FP64) return pcg_impl<double>(p, k, B, X, o, info, st, ahist, bhist);
+  return pcg_impl<float>(p, k, B, X, o, info, st, ahist, bhist);
 }
 
 }  // namespace higp

@@ -37,12 +37,15 @@ struct PcgState {
   double* work;    // reduction partials
   unsigned* counter;
   volatile int* nactive_host;  // optional pinned host copy of *nactive
+  double* ahist;   // optional max_iter×k: α_j of each column (row j)
+  double* bhist;   // optional max_iter×k: β_j of each column (row j)
 };
 
 struct PcgScalars {
   double tol;
   double minv;
   int max_iter;
+  int k;              // columns (row length of the coefficient histories)
   int replaced_only;  // 1: stop on tol only after a residual replacement
   int stall_off;      // 1: stop replacing a column once a replacement stalls
   int general_m;      // 1: ρ = rᵀM⁻¹r comes from a separate dot (pcg_rho_beta)
@@ -68,6 +71,7 @@ __device__ __forceinline__ void pcg_finish_col(const PcgState& S, const PcgScala
   }
   const bool tol_ok = rel <= P.tol && (replaced || !P.replaced_only);
   if (tol_ok || it >= P.max_iter || !(rel < 1e8)) S.active[c] = 0;
+  else if (S.bhist && !P.general_m) S.bhist[(size_t)(it - 1) * P.k + c] = S.beta[c];
 }
 
 __device__ __forceinline__ void pcg_count_active(const PcgState& S, int k) {
@@ -102,6 +106,9 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
     // α = 0 once the residual is exactly zero (pᵀq = 0): x and r stay put.
     const double num = pr ? pr[c] : S.rho[c];
     const double alpha = S.pq[c] != 0.0 ? num / S.pq[c] : 0.0;
+    // The column's iteration count is raised only by the last block, after
+    // every block has passed this point.
+    if (S.ahist && blockIdx.x == 0 && r0 == 0) S.ahist[(size_t)S.iters[c] * k + c] = alpha;
     for (int64_t i = beg + r0; i < end; i += L.step) {
       const int64_t o = i * k + c;
       S.x[o] += alpha * (double)p[o];

@@ -18,8 +18,6 @@
 
 namespace higp {
 
-int run_pcg(const Problem& p, int k, const void* B, void* X, const higp_pcg_opts& o,
-            higp_pcg_info* info, hipStream_t st);
 int host_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, double* out,
                 hipStream_t st);
 int launch_kmatvec_cross(const Problem& p, int64_t m, const void* Xq, int k, const void* V,

@@ -166,9 +166,12 @@ def test_coldot_and_nlml_reject_bad_arguments():
     p = _prob()
     loss = ctypes.c_double()
     g = (ctypes.c_double * 3)()
-    good = dict(tol=1e-6, max_iter=10, precond=1, refine_every=0, nsteps=10, reorth=1, reserved=0)
+    good = dict(tol=1e-6, max_iter=10, precond=1, refine_every=0, nsteps=10, reorth=1,
+                logdet_mode=0, trace_mode=0, reserved=0)
     for bad in (dict(tol=0.0), dict(max_iter=0), dict(precond=3), dict(refine_every=-1),
-                dict(nsteps=0), dict(nsteps=5000), dict(reorth=2), dict(reserved=1)):
+                dict(nsteps=0), dict(nsteps=5000), dict(reorth=2), dict(reserved=1),
+                dict(logdet_mode=2), dict(logdet_mode=-1), dict(trace_mode=2),
+                dict(logdet_mode=1, refine_every=10), dict(logdet_mode=1, trace_mode=1)):
         o = _lib.NlmlOpts(**{**good, **bad})
         rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), 4, ctypes.c_void_p(64),
                          ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
@@ -178,6 +181,12 @@ def test_coldot_and_nlml_reject_bad_arguments():
         rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), N, ctypes.c_void_p(64),
                          ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
         assert rc == _lib.HIGP_ERR_INVALID_ARG
+    # Hutch++ needs a sketch and a remainder (N ≥ 2) and 1 + 3⌊N/2⌋ ≤ 64
+    o = _lib.NlmlOpts(**dict(good, trace_mode=1))
+    for N in (1, 43):
+        rc = L.higp_nlml(ctypes.byref(p), ctypes.c_void_p(16), N, ctypes.c_void_p(64),
+                         ctypes.byref(o), ctypes.byref(loss), g, None, None, None)
+        assert rc == _lib.HIGP_ERR_INVALID_ARG, N
 
 
 def test_request_footprint_host_logic():
