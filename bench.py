@@ -86,9 +86,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the PCG/SLQ wall-time legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the CPU oracle sample (0 = all)")
-    ap.add_argument("--legs", default="fp64,bf16,grad,train,paper,serve",
-                    help="comma list of extra legs (fp64, bf16, grad, train, paper, serve) or "
-                         "'none'")
+    ap.add_argument("--legs", default="fp64,bf16,grad,train,estimators,paper,serve",
+                    help="comma list of extra legs (fp64, bf16, grad, train, estimators, paper, "
+                         "serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
     ap.add_argument("--serve-rank", type=int, default=512,
@@ -241,6 +241,9 @@ def main():
         out["grad_matvec"] = leg_grad()
     if "train" in legs:
         out["train_e2e"] = leg_train()
+        out["train_e2e_cg_logdet"] = leg_train("cg")
+    if "estimators" in legs:
+        out["nlml_estimators"] = leg_estimators()
     if "paper" in legs:
         for kname, kid in (("gaussian", 0), ("matern32", 1)):
             out["paper_shape_e2e_" + kname] = leg_paper_shape(kid)
@@ -375,11 +378,12 @@ def leg_grad():
                 mfma_tflops=4.0 * n * n * k / (ms * 1e-3) / 1e12)
 
 
-def leg_train():
+def leg_train(logdet="slq"):
     """Hyper-parameter training with the paper's end-to-end settings (Adam,
     50 steps, learning rate 0.01, 20 CG iterations per solve, FP32) on the
     n = 100,000 workload (Gaussian, start Θ = (0.1, 1, 0.01)), 16 Rademacher
-    probes, 20 Lanczos steps, Jacobi, softplus parameters."""
+    probes, 20 Lanczos steps (logdet "slq") or the tridiagonals of the 20 CG
+    iterations (logdet "cg"), Jacobi, softplus parameters."""
     import torch
     from paper_2503_02259_amd import workloads as W
     from paper_2503_02259_amd.autograd import GPRModel, train_gpr
@@ -389,16 +393,47 @@ def leg_train():
     y = torch.from_numpy(prob.extra["y"]).to(d, torch.float32)
     Z = torch.from_numpy(prob.extra["Z"][:, :16].copy()).to(d, torch.float32)
     model = GPRModel(X, y, Z, kernel=0, l=prob.l, f=prob.f, s=prob.s,
-                     opts=dict(tol=1e-6, max_iter=20, nsteps=20), transform="softplus")
+                     opts=dict(tol=1e-6, max_iter=20, nsteps=20, logdet=logdet),
+                     transform="softplus")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = train_gpr(model, steps=50, lr=0.01)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    _log("train leg done")
-    return dict(workload="n=100000 d=3 Gaussian, 50 Adam steps lr 0.01, 20 CG its, 16 probes x 20 "
-                         "Lanczos steps, FP32", time_s=t, ms_per_step=1e3 * t / 50,
+    _log("train leg (%s) done" % logdet)
+    return dict(workload="n=100000 d=3 Gaussian, 50 Adam steps lr 0.01, 20 CG its, 16 probes, "
+                         + ("20 Lanczos steps" if logdet == "slq" else "log-det from the CG "
+                            "tridiagonals") + ", FP32", time_s=t, ms_per_step=1e3 * t / 50,
                 loss_first=hist[0]["loss"], loss_last=hist[-1]["loss"], theta_final=model.get_params())
+
+
+def leg_estimators():
+    """One NLML evaluation (loss and gradient) on the n = 100,000 workload
+    (Gaussian, Θ = (0.1, 1, 0.01), FP32) with the E2E settings (16 probes,
+    20 CG iterations, 20 Lanczos steps, Jacobi) for each estimator form:
+    SLQ + Hutchinson, CG tridiagonals + Hutchinson, SLQ + Hutch++."""
+    import torch
+    import paper_2503_02259_amd as hg
+    from paper_2503_02259_amd import workloads as W
+    prob = W.workload_fp32_matvec()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(d, torch.float32)
+    y = torch.from_numpy(prob.extra["y"]).to(d, torch.float32)
+    Z = torch.from_numpy(prob.extra["Z"][:, :16].copy()).to(d, torch.float32)
+    out = {}
+    for name, kw in (("slq_hutchinson", {}), ("cg_logdet_hutchinson", dict(logdet="cg")),
+                     ("slq_hutchpp", dict(trace="hutchpp"))):
+        hg.nlml(X, y, Z, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=20, nsteps=20, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, grad, info = hg.nlml(X, y, Z, 0, prob.l, prob.f, prob.s, tol=1e-6, max_iter=20,
+                                   nsteps=20, **kw)
+        torch.cuda.synchronize()
+        out[name] = dict(time_s=time.perf_counter() - t0, loss=loss, grad=[float(g) for g in grad],
+                         logdet=info["logdet"])
+    _log("estimators leg done")
+    return dict(workload="n=100000 d=3 Gaussian (l, f, s) = (0.1, 1, 0.01), 16 probes, 20 CG its, "
+                         "20 Lanczos steps, Jacobi, FP32", **out)
 
 
 def leg_paper_shape(kernel):
