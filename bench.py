@@ -86,9 +86,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the PCG/SLQ wall-time legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the CPU oracle sample (0 = all)")
-    ap.add_argument("--legs", default="fp64,bf16,grad,train,estimators,paper,serve",
-                    help="comma list of extra legs (fp64, bf16, grad, train, estimators, paper, "
-                         "serve) or 'none'")
+    ap.add_argument("--legs", default="fp64,bf16,grad,sym,train,estimators,paper,serve",
+                    help="comma list of extra legs (fp64, bf16, grad, sym, train, estimators, "
+                         "paper, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
     ap.add_argument("--serve-rank", type=int, default=512,
@@ -244,6 +244,8 @@ def main():
         out["train_e2e_cg_logdet"] = leg_train("cg")
     if "estimators" in legs:
         out["nlml_estimators"] = leg_estimators()
+    if "sym" in legs:
+        out["symmetric_matvec"] = leg_symmetric()
     if "paper" in legs:
         for kname, kid in (("gaussian", 0), ("matern32", 1)):
             out["paper_shape_e2e_" + kname] = leg_paper_shape(kid)
@@ -405,6 +407,39 @@ def leg_train(logdet="slq"):
                          + ("20 Lanczos steps" if logdet == "slq" else "log-det from the CG "
                             "tridiagonals") + ", FP32", time_s=t, ms_per_step=1e3 * t / 50,
                 loss_first=hist[0]["loss"], loss_last=hist[-1]["loss"], theta_final=model.get_params())
+
+
+def leg_symmetric():
+    """k = 1 and k = 2 FP32 MatVecs on the n = 100,000 workload (Gaussian,
+    l = 0.1): the symmetric form (each kernel value of a block pair used for
+    both output blocks) against the full-block form."""
+    import torch
+    import paper_2503_02259_amd as hg
+    from paper_2503_02259_amd import workloads as W
+    prob = W.workload_fp32_matvec()
+    d = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(d, torch.float32)
+    out = {}
+    for k in (1, 2):
+        V = torch.from_numpy(prob.extra["V"][:, :k].copy()).to(d, torch.float32)
+        for sym in (True, False):
+            for _ in range(2):
+                hg.kmatvec(X, V, 0, prob.l, prob.f, prob.s, symmetric=sym)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(10):
+                hg.kmatvec(X, V, 0, prob.l, prob.f, prob.s, symmetric=sym)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            out["k%d_%s_ms" % (k, "symmetric" if sym else "full_block")] = ms
+            out["k%d_%s_kev_vec_per_s" % (k, "symmetric" if sym else "full_block")] = \
+                prob.X.shape[0] ** 2 * k / (ms * 1e-3)
+        out["k%d_speedup" % k] = out["k%d_full_block_ms" % k] / out["k%d_symmetric_ms" % k]
+    _log("symmetric leg done")
+    return dict(workload="n=100000 d=3 Gaussian l=0.1 f=1 s=1e-2, V = first k columns of [y|Z], "
+                         "FP32", **out)
 
 
 def leg_estimators():

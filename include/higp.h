@@ -67,6 +67,17 @@ typedef enum {
                      relative error of order 2⁻¹⁶ instead of 2⁻⁸ */
 } higp_precision;
 
+/* Problem flags.
+ * HIGP_FLAG_NO_SYMMETRIC: the FP32 square MatVec with k ≤ 2 vectors and
+ *   d ≤ 4 at 32768 ≤ n (up to about 4·10⁵ for k = 2, 5.6·10⁵ for k = 1,
+ *   where its per-block-pair slots reach 2 GiB) normally evaluates each
+ *   kernel value of a pair of
+ *   point blocks once and uses it for both output blocks (K̂ is symmetric:
+ *   about n²/2 kernel values instead of n²).  This flag selects the
+ *   full-block form instead, whose summation order is that of the wider
+ *   MatVecs (both forms are deterministic).                                */
+#define HIGP_FLAG_NO_SYMMETRIC 1
+
 /* One GP problem: K̂ = f²·k(X, X; l) + s·I.
  * X: device, n×d row-major (double for HIGP_FP64, float otherwise).
  * Valid: n ≥ 1, 1 ≤ d ≤ HIGP_MAX_D, l > 0, s ≥ 0, f finite.               */
@@ -75,7 +86,7 @@ typedef struct {
   int32_t prec;   /* higp_precision */
   int64_t n;
   int32_t d;
-  int32_t reserved; /* must be 0 */
+  int32_t flags;  /* 0 or HIGP_FLAG_* bits */
   const void* X;
   double l, f, s;
 } higp_problem;

@@ -14,6 +14,7 @@ HIGP_ERR_INVALID_ARG = -1
 HIGP_ERR_UNSUPPORTED = -2
 HIGP_ERR_OOM = -3
 HIGP_ERR_HIP = -4
+HIGP_FLAG_NO_SYMMETRIC = 1
 
 GAUSSIAN = 0
 MATERN32 = 1
@@ -34,7 +35,7 @@ HIGP_REQ_QUEUED, HIGP_REQ_ACTIVE, HIGP_REQ_DONE, HIGP_REQ_FAILED = 0, 1, 2, 3
 
 class Problem(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("prec", ctypes.c_int32), ("n", ctypes.c_int64),
-                ("d", ctypes.c_int32), ("reserved", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("d", ctypes.c_int32), ("flags", ctypes.c_int32), ("X", ctypes.c_void_p),
                 ("l", ctypes.c_double), ("f", ctypes.c_double), ("s", ctypes.c_double)]
 
 

@@ -57,15 +57,17 @@ def _stream(stream, device):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def problem(X, kernel, l, f, s, precision=None):
-    """The ABI problem struct for points X (n×d device tensor)."""
+def problem(X, kernel, l, f, s, precision=None, symmetric=True):
+    """The ABI problem struct for points X (n×d device tensor).
+    symmetric=False selects the full-block FP32 MatVec where the symmetric
+    one would apply (k ≤ 2, d ≤ 4, n ≥ 32768)."""
     if X.dim() != 2:
         raise ValueError("X must be n×d")
     p = _lib.Problem()
     p.kernel = _kernel_id(kernel)
     p.prec = _prec(X, precision)
     p.n, p.d = X.shape
-    p.reserved = 0
+    p.flags = 0 if symmetric else _lib.HIGP_FLAG_NO_SYMMETRIC
     p.X = _dev(X, "X", X.dtype)
     p.l, p.f, p.s = float(l), float(f), float(s)
     return p
@@ -75,9 +77,10 @@ def _as2d(V):
     return (V.unsqueeze(1), True) if V.dim() == 1 else (V, False)
 
 
-def kmatvec(X, V, kernel, l, f, s, precision=None, out=None, stream=None):
-    """Y = K̂·V with K̂ = f²·k(X, X; l) + s·I (on-the-fly; K̂ is never stored)."""
-    p = problem(X, kernel, l, f, s, precision)
+def kmatvec(X, V, kernel, l, f, s, precision=None, out=None, stream=None, symmetric=True):
+    """Y = K̂·V with K̂ = f²·k(X, X; l) + s·I (on-the-fly; K̂ is never stored).
+    symmetric=False: see ``problem``."""
+    p = problem(X, kernel, l, f, s, precision, symmetric)
     V2, squeeze = _as2d(V)
     n, k = V2.shape
     vp = _dev(V2, "V", X.dtype, (p.n, k))

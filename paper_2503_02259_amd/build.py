@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhigp.so")
-SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f32_batch.hip", "kmatvec_f64.hip",
+SOURCES = ["abi.hip", "kmatvec.hip", "kmatvec_f32.hip", "kmatvec_f32_sym.hip",
+           "kmatvec_f32_batch.hip", "kmatvec_f64.hip",
            "nystrom.hip",
            "kmatvec_bf16.hip", "predict.hip", "blas.hip", "pcg.hip", "slq.hip", "nlml.hip",
            "hutchpp.hip", "server.hip"]

@@ -45,7 +45,8 @@ int validate_problem(const higp_problem* p, Problem* out) {
     return set_error(HIGP_ERR_INVALID_ARG, "n = %lld out of range [1, 2^30]", (long long)p->n);
   if (p->d < 1 || p->d > HIGP_MAX_D)
     return set_error(HIGP_ERR_INVALID_ARG, "d = %d out of range [1, %d]", p->d, HIGP_MAX_D);
-  if (p->reserved != 0) return set_error(HIGP_ERR_INVALID_ARG, "reserved field must be 0");
+  if ((p->flags & ~HIGP_FLAG_NO_SYMMETRIC) != 0)
+    return set_error(HIGP_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
   if (!p->X) return set_error(HIGP_ERR_INVALID_ARG, "X is NULL");
   if (!(p->l > 0.0) || !std::isfinite(p->l))
     return set_error(HIGP_ERR_INVALID_ARG, "l must be finite and > 0");
@@ -56,6 +57,7 @@ int validate_problem(const higp_problem* p, Problem* out) {
   out->prec = p->prec;
   out->n = p->n;
   out->d = p->d;
+  out->flags = p->flags;
   out->X = p->X;
   out->l = p->l;
   out->f = p->f;

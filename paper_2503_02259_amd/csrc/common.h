@@ -43,6 +43,7 @@ struct Problem {
   int prec;    // HIGP_FP64 / HIGP_FP32 / HIGP_BF16 / HIGP_BF16X3
   int64_t n;
   int d;
+  int flags = 0;  // HIGP_FLAG_* bits
   const void* X;
   double l, f, s;
 };

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def _prob(**kw):
-    p = _lib.Problem(kernel=0, prec=1, n=10, d=3, reserved=0, X=ctypes.c_void_p(0x1000),
+    p = _lib.Problem(kernel=0, prec=1, n=10, d=3, flags=0, X=ctypes.c_void_p(0x1000),
                      l=0.5, f=1.0, s=0.01)
     for k, v in kw.items():
         setattr(p, k, v)
@@ -40,7 +40,8 @@ def _prob(**kw):
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("n", -5), ("d", 0), ("d", 33), ("l", 0.0),
                                          ("l", -1.0), ("s", -1e-3), ("kernel", 7), ("prec", 5),
-                                         ("reserved", 1), ("X", None), ("l", float("nan")),
+                                         ("flags", 2), ("flags", -1), ("X", None),
+                                         ("l", float("nan")),
                                          ("f", float("inf"))])
 def test_kmatvec_rejects_bad_problem(field, value):
     L = _lib.lib()

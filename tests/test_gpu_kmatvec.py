@@ -121,3 +121,32 @@ def test_bf16_and_server_reject_high_dimension():
         srv.submit(X, V[:, 0].contiguous())
     assert e.value.code == -2
     srv.close()
+
+
+SYM = [(40_000, 3, 1), (40_000, 3, 2), (33_001, 1, 1), (35_000, 2, 2), (32_768, 4, 1),
+       (50_000, 4, 2)]
+
+
+@pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
+@pytest.mark.parametrize("n,d,k", SYM)
+def test_symmetric_fp32_matvec(n, d, k, kernel):
+    # k ≤ 2, d ≤ 4, n ≥ 32768: each kernel value of a block pair serves both
+    # output blocks.  Rows checked against the oracle where super blocks
+    # (1024 points) and tiles (128) meet, at both ends and in the ragged last
+    # block; every row against the full-block form.
+    X = as_prec(W.uniform_points(n, d, 700 + d), torch.float32)
+    V = as_prec(W.rng(700 + k, 4).standard_normal((n, k)), torch.float32)
+    l, f, s = 0.15, 1.1, 0.02
+    Xd, Vd = to_dev(X, torch.float32), to_dev(V, torch.float32)
+    Y = hg.kmatvec(Xd, Vd, kernel, l, f, s).cpu().numpy()
+    Yf = hg.kmatvec(Xd, Vd, kernel, l, f, s, symmetric=False).cpu().numpy()
+    for rows in (slice(0, 130), slice(1000, 1160), slice(n // 2 - 70, n // 2 + 70),
+                 slice(n - 200, n)):
+        ref = oracle_rows(X, V, kernel, l, f, s, rows)
+        err = colrel(Y[rows], ref).max()
+        assert err <= 1e-5, (rows, err)
+    diff = colrel(Y, Yf).max()
+    print("n=%d d=%d k=%d: symmetric vs full-block %.2e" % (n, d, k, diff))
+    assert diff <= 2e-6
+    # deterministic
+    assert np.array_equal(Y, hg.kmatvec(Xd, Vd, kernel, l, f, s).cpu().numpy())
