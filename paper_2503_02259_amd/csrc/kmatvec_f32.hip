@@ -215,9 +215,6 @@ static int run_f32(const Problem& p, int64_t m, const float* Xq, int k, const vo
   return rc;
 }
 
-bool kmatvec_f32_sym_applies(const Problem& p, int k);
-int launch_kmatvec_f32_sym(const Problem& p, int k, const void* V, void* Y, hipStream_t st);
-
 int launch_kmatvec_f32(const Problem& p, int k, const void* V, MatvecOut out, hipStream_t st,
                        int num_cus) {
   if (out.kv && !out.dl && !out.df && kmatvec_f32_sym_applies(p, k))

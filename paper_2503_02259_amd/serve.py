@@ -31,12 +31,13 @@ class Server:
         self._keep = {}
 
     def submit(self, X, y, Z=None, l=0.1, f=1.0, s=1e-2, kernel=0, tol=1e-6, max_iter=1000,
-               nsteps=40, precond_rank=0):
+               nsteps=40, precond_rank=0, symmetric=True):
         """Queue a solve; returns its id.  X (n×d), y (n), Z (n×nprobe) are
         float32 device tensors kept alive until the request is done.
         precond_rank > 0 solves with the Nyström preconditioner of that rank
-        instead of Jacobi."""
-        p = problem(X, kernel, l, f, s, "fp32")
+        instead of Jacobi.  symmetric=False keeps a large request's
+        single-column MatVecs in the full-block form."""
+        p = problem(X, kernel, l, f, s, "fp32", symmetric)
         x_out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
         nprobe = 0 if Z is None else Z.shape[1]
         r = _lib.Request(p=p, y=_dev(y, "y", torch.float32, (X.shape[0],)),
