@@ -82,6 +82,7 @@ struct BatchMatvec {
   float* Y;
   int64_t n;
   int k, d, kernel;
+  int flags;  // HIGP_FLAG_* of the problem
   double f, s;
 };
 size_t prepared_points_bytes(int64_t n, int d);

@@ -1,9 +1,10 @@
 // Batched FP32 on-the-fly MatVec of many independent problems (continuous-
-// batching serving), built on the tile unit of the single-problem MatVec.
+// batching serving), built on the tile unit of the single-problem MatVec and
+// (for large single-column problems) on the symmetric block-pair unit.
 #include <algorithm>
 #include <vector>
 
-#include "kmv_f32_tile.h"
+#include "kmv_f32_sym.h"
 
 namespace higp {
 namespace {
@@ -78,6 +79,58 @@ __global__ __launch_bounds__(256) void kmv_f32_batch(const BatchJob* __restrict_
       batch_unit<HIGP_GAUSSIAN, KIND>(a, jobs[lo].dcode, rt, split, smem);
     else
       batch_unit<HIGP_MATERN32, KIND>(a, jobs[lo].dcode, rt, split, smem);
+    __syncthreads();
+  }
+}
+
+// Kind 3: single-column problems large enough for the symmetric form; a
+// work unit is one block pair (A ≤ B) of one problem (kmv_f32_sym.h).  A
+// problem's pairs and their slots depend only on its own n, so its result
+// does not depend on the rest of the batch either.
+struct SymJob {
+  SymArgs a;
+  int64_t first_unit;  // units of earlier jobs of the same launch
+  int kernel;
+  int dcode;           // 2, 3 or 4
+};
+
+template <int KERN, bool DIAG>
+__device__ __forceinline__ void sym_unit(const SymArgs& a, int dcode, int A, int B, int64_t item,
+                                         SymLds<1>& L) {
+  if (dcode == 2) sym_pair<KERN, 2, 1, DIAG>(a, A, B, item, L);
+  else if (dcode == 3) sym_pair<KERN, 3, 1, DIAG>(a, A, B, item, L);
+  else sym_pair<KERN, 4, 1, DIAG>(a, A, B, item, L);
+}
+
+__global__ __launch_bounds__(256) void kmv_f32_batch_sym(const SymJob* __restrict__ jobs,
+                                                         int njobs, int64_t total,
+                                                         unsigned long long* counter) {
+  __shared__ SymLds<1> L;
+  __shared__ long long unit_sh;
+  for (;;) {
+    if (threadIdx.x == 0) unit_sh = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t u = unit_sh;
+    __syncthreads();
+    if (u >= total) break;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (jobs[mid].first_unit <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const SymArgs a = jobs[lo].a;
+    const int dcode = jobs[lo].dcode;
+    const int64_t item = u - jobs[lo].first_unit;
+    int A, B;
+    item_pair((int)item, a.ns, A, B);
+    if (jobs[lo].kernel == HIGP_GAUSSIAN) {
+      if (A == B) sym_unit<HIGP_GAUSSIAN, true>(a, dcode, A, B, item, L);
+      else sym_unit<HIGP_GAUSSIAN, false>(a, dcode, A, B, item, L);
+    } else {
+      if (A == B) sym_unit<HIGP_MATERN32, true>(a, dcode, A, B, item, L);
+      else sym_unit<HIGP_MATERN32, false>(a, dcode, A, B, item, L);
+    }
     __syncthreads();
   }
 }
@@ -164,18 +217,93 @@ int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const B
   return rc;
 }
 
+int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st, int num_cus) {
+  const int count = (int)src.size();
+  if (count == 0) return HIGP_OK;
+  std::vector<SymJob> hj(count);
+  std::vector<size_t> slot_off(count);
+  int64_t total = 0;
+  size_t slots = 0;  // floats per slot array (rows and columns each)
+  for (int i = 0; i < count; ++i) {
+    const BatchMatvec& J = *src[i];
+    const int ns = (int)((J.n + kSymSuper - 1) / kSymSuper);
+    const int64_t items = (int64_t)ns * (ns + 1) / 2;
+    SymJob b{};
+    b.a.Xp = J.Xp;
+    b.a.V = J.V;
+    b.a.n = J.n;
+    b.a.ns = ns;
+    b.first_unit = total;
+    b.kernel = J.kernel;
+    b.dcode = J.d <= 2 ? 2 : (J.d == 3 ? 3 : 4);
+    hj[i] = b;
+    slot_off[i] = slots;
+    total += items;
+    slots += (size_t)items * kSymSuper;
+  }
+  const size_t jobs_bytes = ((size_t)count * sizeof(SymJob) + 255) / 256 * 256;
+  void* mem = nullptr;
+  HIGP_TRY(scratch_alloc(&mem, jobs_bytes + 256 + 2 * slots * 4, st));
+  char* base = static_cast<char*>(mem);
+  SymJob* djobs = reinterpret_cast<SymJob*>(base);
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(base + jobs_bytes);
+  float* prow = reinterpret_cast<float*>(base + jobs_bytes + 256);
+  float* pcol = prow + slots;
+  for (int i = 0; i < count; ++i) {
+    hj[i].a.prow = prow + slot_off[i];
+    hj[i].a.pcol = pcol + slot_off[i];
+  }
+  int rc = HIGP_OK;
+  if (hipMemcpyAsync(djobs, hj.data(), count * sizeof(SymJob), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
+    rc = set_error(HIGP_ERR_HIP, "batch setup failed");
+  static int bpc = 0;
+  if (bpc == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(kmv_f32_batch_sym), 256, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    bpc = nb;
+  }
+  if (rc == HIGP_OK) {
+    const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
+    hipLaunchKernelGGL(kmv_f32_batch_sym, dim3((unsigned)grid), dim3(256), 0, st,
+                       (const SymJob*)djobs, count, total, counter);
+    for (int i = 0; i < count; ++i) {
+      const BatchMatvec& J = *src[i];
+      const unsigned fb = (unsigned)std::min<int64_t>((J.n + 255) / 256, 2LL * num_cus);
+      hipLaunchKernelGGL(kmv_f32_sym_finish<1>, dim3(fb), dim3(256), 0, st, J.n, hj[i].a.ns,
+                         (const float*)hj[i].a.prow, (const float*)hj[i].a.pcol, J.V, J.Y,
+                         J.f * J.f, J.s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      rc = set_error(HIGP_ERR_HIP, "batched symmetric MatVec launch failed: %s",
+                     hipGetErrorString(e));
+  }
+  scratch_free(mem, st);
+  return rc;
+}
+
 }  // namespace
 
 int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus) {
   if (count <= 0) return HIGP_OK;
   std::vector<BatchJob> hj[3];
   std::vector<const BatchMatvec*> src[3];
+  std::vector<const BatchMatvec*> sym;
   int64_t total[3] = {0, 0, 0};
   size_t part_elems[3] = {0, 0, 0};
   for (int i = 0; i < count; ++i) {
     const BatchMatvec& J = jobs[i];
     if (J.k < 1 || J.k > 32)
       return set_error(HIGP_ERR_UNSUPPORTED, "batched MatVec supports 1 <= k <= 32");
+    if (J.k == 1 && sym_eligible(J.n, J.d, 1, J.flags)) {
+      sym.push_back(&J);
+      continue;
+    }
     const int kind = J.k == 1 ? 1 : (J.k == 2 ? 2 : 0);
     const int S = batch_splits(J.n);
     const int64_t jt = (J.n + kBJ - 1) / kBJ;
@@ -202,6 +330,7 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
   HIGP_TRY(launch_batch_kind<0>(hj[0], src[0], total[0], part_elems[0], st, num_cus));
   HIGP_TRY(launch_batch_kind<1>(hj[1], src[1], total[1], part_elems[1], st, num_cus));
   HIGP_TRY(launch_batch_kind<2>(hj[2], src[2], total[2], part_elems[2], st, num_cus));
+  HIGP_TRY(launch_batch_sym(sym, st, num_cus));
   return HIGP_OK;
 }
 

@@ -320,23 +320,17 @@ int run_round(Server& sv) {
   }
   if (sv.active.empty()) return HIGP_OK;
 
-  // 2. One batched MatVec for every active request; a large request whose
-  //    only live column is the CG direction takes the symmetric-tiled
-  //    MatVec instead (its own launch: it fills the chip by itself).
+  // 2. One batched MatVec for every active request (one persistent launch
+  //    per column kind; large single-column requests take the symmetric
+  //    block-pair kind).
   std::vector<BatchMatvec> jobs;
   std::vector<Request*> owners;
-  std::vector<Request*> sym_owners;
   for (auto& up : sv.active) {
     Request& r = *up;
     const int cg = r.cg_active ? 1 : 0;
     const int lz = r.lz_active ? 1 : 0;
     const int kr = cg + lz * r.N;
     if (kr == 0) continue;
-    if (kr == 1 && cg && kmatvec_f32_sym_applies(r.p, 1)) {
-      HIGP_TRY(launch_kmatvec_f32_sym(r.p, 1, r.cg_p, r.cg_q, st));
-      sym_owners.push_back(&r);
-      continue;
-    }
     const int64_t count_pad = (r.p.n * kr + 3) / 4 * 4;
     hipLaunchKernelGGL(srv_pack, dim3(elem_blocks(count_pad)), dim3(256), 0, st, r.p.n, kr, cg,
                        r.N > 0 ? r.N : 1, (const float*)r.cg_p, (const float*)r.QW, r.Vin,
@@ -349,27 +343,23 @@ int run_round(Server& sv) {
     j.k = kr;
     j.d = r.p.d;
     j.kernel = r.p.kernel;
+    j.flags = r.p.flags;
     j.f = r.p.f;
     j.s = r.p.s;
     jobs.push_back(j);
     owners.push_back(&r);
   }
-  if (!jobs.empty())
-    HIGP_TRY(launch_kmatvec_f32_batch(jobs.data(), (int)jobs.size(), st, sv.num_cus));
-  const size_t nbatch = owners.size();
-  owners.insert(owners.end(), sym_owners.begin(), sym_owners.end());
+  HIGP_TRY(launch_kmatvec_f32_batch(jobs.data(), (int)jobs.size(), st, sv.num_cus));
 
   // 3. Per-request CG and Lanczos updates.
   for (size_t q = 0; q < owners.size(); ++q) {
     Request& r = *owners[q];
     const int cg = r.cg_active ? 1 : 0;
     const int lz = r.lz_active ? 1 : 0;
+    const int kr = jobs[q].k;
     const int64_t n = r.p.n;
-    if (q < nbatch) {  // symmetric requests wrote K̂p straight into cg_q
-      const int kr = jobs[q].k;
-      hipLaunchKernelGGL(srv_unpack, dim3(elem_blocks(n * kr)), dim3(256), 0, st, n, kr, cg,
-                         r.N > 0 ? r.N : 1, lz, (const float*)r.Vout, r.cg_q, r.WW);
-    }
+    hipLaunchKernelGGL(srv_unpack, dim3(elem_blocks(n * kr)), dim3(256), 0, st, n, kr, cg,
+                       r.N > 0 ? r.N : 1, lz, (const float*)r.Vout, r.cg_q, r.WW);
     if (cg) {
       const RedGrid g = red_grid(n);
       HIGP_TRY(launch_coldot(n, 1, r.cg_p, 1, r.cg_q, 1, r.S.pq, r.S.work, r.S.counter, st));
