@@ -316,10 +316,18 @@ def leg_fp64():
     t0 = time.perf_counter()
     ld, per = hg.slq_logdet(X, Z, p.kernel, p.l, p.f, p.s, 30)
     t_slq = time.perf_counter() - t0
+    # The FP64 MatVec at the n = 100,000, k = 33 shape (the residual
+    # replacement of the refined solves uses it every 10 iterations).
+    q = W.workload_fp32_matvec()
+    Xq = torch.from_numpy(q.X).to(d)
+    Vq = torch.from_numpy(q.extra["V"]).to(d)
+    ms_big = _timed(lambda: hg.kmatvec(Xq, Vq, q.kernel, q.l, q.f, q.s), 5)
     _log("fp64 leg done")
     return dict(workload="n=2000 d=3 Gaussian f=1 l=0.5 s=0.01, FP64", matvec_ms=ms,
                 cg_time_to_1em8_s=t_cg, cg_iters=int(info["iters"]),
-                slq_10x30_time_s=t_slq, slq_logdet=ld, pipeline_s=ms * 1e-3 + t_cg + t_slq)
+                slq_10x30_time_s=t_slq, slq_logdet=ld, pipeline_s=ms * 1e-3 + t_cg + t_slq,
+                matvec_n100000_k33_ms=ms_big,
+                matvec_n100000_k33_tflops=2 * q.X.shape[0] ** 2 * 33 / (ms_big * 1e-3) / 1e12)
 
 
 def leg_bf16():

@@ -38,14 +38,16 @@ struct KArgs {
 // FP64: v_mfma_f64_16x16x4f64.  A wave owns 16 rows; per MFMA each lane
 // supplies K[i0 + lane%16][j0 + lane/16] (4 J points per step); NB blocks of
 // 16 columns.  Output layout: lane l, register r holds row l/16 + 4r,
-// column l%16.
+// column l%16.  With NV = 1 one more column (k = 16·NB + 1, e.g. y plus 16
+// or 32 probes) is carried on the VALU: each lane adds its kernel values
+// times that column's V, and the 4 lanes of a row are added at the end.
 
 constexpr int kBJ64 = 64;  // J points per LDS tile (FP64 kernel)
 
-template <int KERN, int D, int NB, bool GRAD>
+template <int KERN, int D, int NB, int NV, bool GRAD>
 __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   constexpr int P = D <= 4 ? 4 : (D <= 8 ? 8 : (D + 3) / 4 * 4);
-  constexpr int VC = NB * 16;
+  constexpr int VC = NB * 16 + NV;
   constexpr int BM = 16 * kWaves;
   __shared__ double Xs[2][kBJ64][P];
   __shared__ double Vs[2][kBJ64][VC];
@@ -74,6 +76,7 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
     acc[b] = f64x4{0};
     if constexpr (GRAD) acc2[b] = f64x4{0};
   }
+  double accx = 0.0, accx2 = 0.0;  // the VALU column (NV = 1)
 
   constexpr int XPER = (kBJ64 * D + 255) / 256;
   constexpr int VROWS = kBJ64 / 4;
@@ -148,6 +151,11 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
         acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, vb, acc[b], 0, 0, 0);
         if constexpr (GRAD) acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kg, vb, acc2[b], 0, 0, 0);
       }
+      if constexpr (NV == 1) {
+        const double vx = Vs[cur][j][NB * 16];
+        accx = fma(kv, vx, accx);
+        if constexpr (GRAD) accx2 = fma(kg, vx, accx2);
+      }
     }
 
     if (more) lstore(cur ^ 1);
@@ -159,6 +167,29 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   double* p2 = a.o2;
   if constexpr (GRAD) {
     if (!direct) p2 = a.o2 + (int64_t)split * a.m * k;
+  }
+  if constexpr (NV == 1) {
+    // Row l16's VALU column: the 4 lanes l16 + 16q hold its J points ≡ q mod 4.
+    accx += __shfl_xor(accx, 16);
+    accx += __shfl_xor(accx, 32);
+    if constexpr (GRAD) {
+      accx2 += __shfl_xor(accx2, 16);
+      accx2 += __shfl_xor(accx2, 32);
+    }
+    const int col = NB * 16;
+    if (q == 0 && irow < a.m && col < k) {
+      const int64_t o = irow * k + col;
+      if (direct) {
+        if (a.o1) a.o1[o] = fma(a.f2, accx, a.sV ? a.s * a.sV[o] : 0.0);
+        if constexpr (GRAD) {
+          if (a.o2) a.o2[o] = a.cl * accx2;
+          if (a.o3) a.o3[o] = a.cf * accx;
+        }
+      } else {
+        p1[o] = accx;
+        if constexpr (GRAD) p2[o] = accx2;
+      }
+    }
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -213,10 +244,13 @@ using KFn = void (*)(KArgs<T>);
 
 template <int KERN, int D, bool GRAD>
 KFn<double> pick_f64_cols(int k) {
-  if (k <= 16) return kmv_f64<KERN, D, 1, GRAD>;
-  if (k <= 32) return kmv_f64<KERN, D, 2, GRAD>;
-  if (k <= 48) return kmv_f64<KERN, D, 3, GRAD>;
-  return kmv_f64<KERN, D, 4, GRAD>;
+  if (k <= 16) return kmv_f64<KERN, D, 1, 0, GRAD>;
+  if (k == 17) return kmv_f64<KERN, D, 1, 1, GRAD>;
+  if (k <= 32) return kmv_f64<KERN, D, 2, 0, GRAD>;
+  if (k == 33) return kmv_f64<KERN, D, 2, 1, GRAD>;
+  if (k <= 48) return kmv_f64<KERN, D, 3, 0, GRAD>;
+  if (k == 49) return kmv_f64<KERN, D, 3, 1, GRAD>;
+  return kmv_f64<KERN, D, 4, 0, GRAD>;
 }
 
 template <int KERN, bool GRAD>

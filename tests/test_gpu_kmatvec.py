@@ -15,7 +15,8 @@ from helpers import TOL, as_prec, colrel, colrel_cond, oracle_rows, to_dev
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(1, 1, 1), (2, 3, 2), (127, 3, 33), (1001, 3, 17), (300, 1, 5), (517, 2, 64),
-          (700, 8, 31), (640, 5, 32), (333, 4, 63), (999, 3, 34), (260, 7, 10), (2000, 3, 1)]
+          (700, 8, 31), (640, 5, 32), (333, 4, 63), (999, 3, 34), (260, 7, 10), (2000, 3, 1),
+          (777, 3, 49)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
