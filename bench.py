@@ -196,6 +196,14 @@ def main():
                              "bytes_moved": int(X.numel() * 4 + 2 * V.numel() * 4)}
     del Xh, Vh, Yh, Xd, Vd
 
+    # The other kernel of the same configuration (Matérn-3/2 when the headline
+    # is Gaussian and the reverse), same points and vectors.
+    other = hg.MATERN32 if kern == hg.GAUSSIAN else hg.GAUSSIAN
+    ms_o = _timed(lambda: hg.kmatvec(X, V, other, prob.l, prob.f, prob.s, out=Y), 10)
+    out["other_kernel"] = {"kernel": "matern32" if other == hg.MATERN32 else "gaussian", "ms": ms_o,
+                           "kev_vec_per_s": float(n) * n * k / (ms_o * 1e-3),
+                           "mfma_frac": 2.0 * n * n * k / (ms_o * 1e-3) / PEAK_MFMA_FP32}
+
     if not args.no_solve:
         # Time to 1e-6: the FP32 form stops on its recursive residual (its
         # true residual is limited by the FP32 floor and reported beside it);
