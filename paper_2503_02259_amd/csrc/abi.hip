@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, error reporting, scratch memory.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,7 +22,7 @@ int host_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, 
 
 namespace {
 thread_local char g_msg[512] = "";
-bool g_pool_ready[64] = {false};
+std::atomic<bool> g_pool_ready[64];  // per device: release threshold raised
 }  // namespace
 
 int set_error(int code, const char* fmt, ...) {
@@ -68,7 +69,7 @@ int validate_problem(const higp_problem* p, Problem* out) {
 int scratch_alloc(void** ptr, size_t bytes, hipStream_t st) {
   int dev = 0;
   HIGP_HIP_TRY(hipGetDevice(&dev));
-  if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
+  if (dev >= 0 && dev < 64 && !g_pool_ready[dev].load(std::memory_order_acquire)) {
     // Keep freed stream-ordered memory in the pool between calls instead of
     // returning it to the driver at every synchronisation.
     hipMemPool_t pool;
@@ -76,7 +77,7 @@ int scratch_alloc(void** ptr, size_t bytes, hipStream_t st) {
       uint64_t thr = UINT64_MAX;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
-    g_pool_ready[dev] = true;
+    g_pool_ready[dev].store(true, std::memory_order_release);
   }
   hipError_t e = hipMallocAsync(ptr, bytes ? bytes : 256, st);
   if (e != hipSuccess) {

@@ -1,4 +1,6 @@
 // Dispatch of the on-the-fly kernel MatVec to its precision forms.
+#include <atomic>
+
 #include "common.h"
 
 namespace higp {
@@ -17,17 +19,17 @@ int launch_kmatvec_f64_cross(const Problem& p, int64_t m, const void* Xq, int k,
 namespace {
 
 int num_cus_impl() {
-  static int cached[64] = {0};
+  static std::atomic<int> cached[64];  // per device; 0 = not yet queried
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int cus = 0;
+  int cus = cached[dev].load(std::memory_order_relaxed);
+  if (cus == 0) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    cached[dev] = cus;
+    cached[dev].store(cus, std::memory_order_relaxed);
   }
-  return cached[dev];
+  return cus;
 }
 
 int num_cus() { return num_cus_impl(); }

@@ -2,6 +2,7 @@
 // batching serving), built on the tile unit of the single-problem MatVec and
 // (for large single-column problems) on the symmetric block-pair unit.
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "kmv_f32_sym.h"
@@ -164,6 +165,19 @@ int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st) {
 
 namespace {
 
+// Resident 256-thread workgroups per CU of a persistent kernel: a property of
+// the kernel and the architecture, so it is computed once per process (the
+// cache is atomic: launches may come from several host threads).
+int resident_blocks(const void* fn, size_t lds, std::atomic<int>& cache) {
+  const int v = cache.load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess || nb < 1)
+    nb = 1;
+  cache.store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
 template <int KIND>
 int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const BatchMatvec*>& src,
                       int64_t total, size_t part_elems, hipStream_t st, int num_cus) {
@@ -188,15 +202,8 @@ int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const B
       hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
     rc = set_error(HIGP_ERR_HIP, "batch setup failed");
   const size_t lds = kind_lds<KIND>();
-  static int bpc = 0;
-  if (bpc == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void*>(kmv_f32_batch<KIND>), 256, lds) != hipSuccess ||
-        nb < 1)
-      nb = 1;
-    bpc = nb;
-  }
+  static std::atomic<int> cache{0};
+  const int bpc = resident_blocks(reinterpret_cast<const void*>(kmv_f32_batch<KIND>), lds, cache);
   if (rc == HIGP_OK) {
     const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
     hipLaunchKernelGGL(kmv_f32_batch<KIND>, dim3((unsigned)grid), dim3(256), lds, st,
@@ -258,15 +265,8 @@ int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st,
           hipSuccess ||
       hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
     rc = set_error(HIGP_ERR_HIP, "batch setup failed");
-  static int bpc = 0;
-  if (bpc == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void*>(kmv_f32_batch_sym), 256, 0) != hipSuccess ||
-        nb < 1)
-      nb = 1;
-    bpc = nb;
-  }
+  static std::atomic<int> cache{0};
+  const int bpc = resident_blocks(reinterpret_cast<const void*>(kmv_f32_batch_sym), 0, cache);
   if (rc == HIGP_OK) {
     const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
     hipLaunchKernelGGL(kmv_f32_batch_sym, dim3((unsigned)grid), dim3(256), 0, st,
