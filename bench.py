@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
     ap.add_argument("--serve-rank", type=int, default=512,
-                    help="Nyström rank of the second serving replay")
+                    help="Nyström rank of the second serving replay (0: skip it)")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
                     help="time only this form's MatVec on the n=500,000 d=8 mixture "
                          "(for profiling) and print its own JSON line")
@@ -259,7 +259,8 @@ def main():
             out["paper_shape_e2e_" + kname] = leg_paper_shape(kid)
     if "serve" in legs and args.serve > 0:
         out["serving"] = leg_serve(args.serve)
-        out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank)
+        if args.serve_rank > 0:
+            out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
