@@ -50,40 +50,59 @@ __global__ __launch_bounds__(256) void kmv_f32(Args a) {
                                                   smem);
 }
 
+template <int KERN, int D, int NV, int RB, bool GRAD, bool EXACT>
+__global__ __launch_bounds__(256) void kmv_f32_16(Args a) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  kmv_f32_unit16<KERN, D, NV, RB, GRAD, EXACT>(a, blockIdx.x / a.nsplit, blockIdx.x % a.nsplit,
+                                               smem);
+}
+
 using Fn = void (*)(Args);
 
+// Instances; *bm receives the rows per workgroup.
 template <int KERN, int D, int NB, int NV, bool GRAD, bool EXACT>
-Fn inst(int* rb) {
+Fn inst(int* bm) {
   constexpr int RB = (NB == 2 || GRAD) ? 1 : 2;
-  *rb = RB;
+  *bm = 32 * RB * kWaves;
   return kmv_f32<KERN, D, NB, NV, RB, GRAD, EXACT>;
 }
 
-// Column blocking: NB blocks of 32 MFMA columns and NV ≤ 2 VALU columns.
-// EXACT instances (k = 1, 2, 32, 33, 34, 64) know the V row stride at
-// compile time.
+template <int KERN, int D, int NV, bool GRAD, bool EXACT>
+Fn inst16(int* bm) {
+  constexpr int RB = (GRAD || D > 8) ? 2 : 4;
+  *bm = 16 * RB * kWaves;
+  return kmv_f32_16<KERN, D, NV, RB, GRAD, EXACT>;
+}
+
+// Column blocking: k ≤ 2 on the VALU; 3 ≤ k ≤ 17 one 16-column MFMA block
+// (plus one VALU column for k = 17); otherwise NB blocks of 32 MFMA columns
+// and NV ≤ 2 VALU columns.  EXACT instances (k = 1, 2, 16, 17, 32, 33, 34,
+// 64) know the V row stride at compile time.
 template <int KERN, int D, bool GRAD>
-Fn pick_cols(int k, int* rb) {
-  if (k == 1) return inst<KERN, D, 0, 1, GRAD, true>(rb);
-  if (k == 2) return inst<KERN, D, 0, 2, GRAD, true>(rb);
-  if (k == 32) return inst<KERN, D, 1, 0, GRAD, true>(rb);
-  if (k < 32) return inst<KERN, D, 1, 0, GRAD, false>(rb);
-  if (k == 33) return inst<KERN, D, 1, 1, GRAD, true>(rb);
-  if (k == 34) return inst<KERN, D, 1, 2, GRAD, true>(rb);
-  if (k == 64) return inst<KERN, D, 2, 0, GRAD, true>(rb);
-  return inst<KERN, D, 2, 0, GRAD, false>(rb);
+Fn pick_cols(int k, int* bm) {
+  if (k == 1) return inst<KERN, D, 0, 1, GRAD, true>(bm);
+  if (k == 2) return inst<KERN, D, 0, 2, GRAD, true>(bm);
+  if (k == 16) return inst16<KERN, D, 0, GRAD, true>(bm);
+  if (k < 16) return inst16<KERN, D, 0, GRAD, false>(bm);
+  if (k == 17) return inst16<KERN, D, 1, GRAD, true>(bm);
+  if (k == 32) return inst<KERN, D, 1, 0, GRAD, true>(bm);
+  if (k < 32) return inst<KERN, D, 1, 0, GRAD, false>(bm);
+  if (k == 33) return inst<KERN, D, 1, 1, GRAD, true>(bm);
+  if (k == 34) return inst<KERN, D, 1, 2, GRAD, true>(bm);
+  if (k == 64) return inst<KERN, D, 2, 0, GRAD, true>(bm);
+  return inst<KERN, D, 2, 0, GRAD, false>(bm);
 }
 
 template <int KERN, bool GRAD>
-Fn pick_d(int d, int k, int* rb) {
+Fn pick_d(int d, int k, int* bm) {
   switch (dim_code(d)) {
-    case 2: return pick_cols<KERN, 2, GRAD>(k, rb);
-    case 3: return pick_cols<KERN, 3, GRAD>(k, rb);
-    case 4: return pick_cols<KERN, 4, GRAD>(k, rb);
-    case 8: return pick_cols<KERN, 8, GRAD>(k, rb);
-    case 16: return pick_cols<KERN, 16, GRAD>(k, rb);
-    case 20: return pick_cols<KERN, 20, GRAD>(k, rb);
-    default: return pick_cols<KERN, 32, GRAD>(k, rb);
+    case 2: return pick_cols<KERN, 2, GRAD>(k, bm);
+    case 3: return pick_cols<KERN, 3, GRAD>(k, bm);
+    case 4: return pick_cols<KERN, 4, GRAD>(k, bm);
+    case 8: return pick_cols<KERN, 8, GRAD>(k, bm);
+    case 16: return pick_cols<KERN, 16, GRAD>(k, bm);
+    case 20: return pick_cols<KERN, 20, GRAD>(k, bm);
+    default: return pick_cols<KERN, 32, GRAD>(k, bm);
   }
 }
 
@@ -120,16 +139,15 @@ static int run_f32(const Problem& p, int64_t m, const float* Xq, int k, const vo
   const bool grad = out.dl != nullptr || out.df != nullptr;
   const bool cross = Xq != nullptr;
   const int64_t rows = cross ? m : p.n;
-  int rb = 1;
+  int bm = 0;
   Fn fn;
   if (p.kernel == HIGP_GAUSSIAN)
-    fn = grad ? pick_d<HIGP_GAUSSIAN, true>(p.d, k, &rb) : pick_d<HIGP_GAUSSIAN, false>(p.d, k, &rb);
+    fn = grad ? pick_d<HIGP_GAUSSIAN, true>(p.d, k, &bm) : pick_d<HIGP_GAUSSIAN, false>(p.d, k, &bm);
   else
-    fn = grad ? pick_d<HIGP_MATERN32, true>(p.d, k, &rb) : pick_d<HIGP_MATERN32, false>(p.d, k, &rb);
+    fn = grad ? pick_d<HIGP_MATERN32, true>(p.d, k, &bm) : pick_d<HIGP_MATERN32, false>(p.d, k, &bm);
   const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
   const double cl = p.f * p.f * dl_factor(p.kernel, HIGP_FP32, p.l);
 
-  const int bm = 32 * rb * kWaves;
   const int P = pad_dim(dim_code(p.d));
   const int64_t nk = p.n * k;   // V elements
   const int64_t mk = rows * k;  // Y elements

@@ -257,6 +257,191 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
   flush();
 }
 
+// The 16-column form for k ≤ 16 (+ NV ≤ 1 VALU column): v_mfma_f32_16x16x4f32
+// does half the MACs of the 32×32×2 form per kernel value, so a MatVec of 16
+// or 17 vectors (16 Lanczos probes; y and 16 probes) needs half the MFMA time.
+// A wave's row block is 16 rows; per step (4 J points) each lane forms
+// K[i0 + lane%16][j0 + lane/16] for each of its RB row blocks as the A
+// operand, against V[j0 + lane/16][lane%16] from LDS as the B operand; the
+// accumulator holds row 4·(lane/16) + r, column lane%16 in register r.  The
+// VALU column is added per lane and the 4 lanes of a row are summed at the
+// end.  Accumulation as in the 32-column form: FP32 within a J tile, FP64
+// running totals across tiles.
+template <int KERN, int D, int NV, int RB, bool GRAD, bool EXACT>
+__device__ __forceinline__ void kmv_f32_unit16(const Args& a, int64_t rt, int split,
+                                               float* smem) {
+  constexpr int P = pad_dim(D);
+  constexpr int BM = 16 * RB * kWaves;
+  constexpr int NVa = NV > 0 ? NV : 1;
+  constexpr int G2 = GRAD ? 2 : 1;
+  constexpr int KMAX = 16 + NV;
+  const int k = EXACT ? KMAX : a.k;
+  const int vtile = kBJ * k;
+  float* Xs = smem;                // [2][kBJ][P]
+  float* Vs = smem + 2 * kBJ * P;  // [2][kBJ·k]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int l16 = lane & 15;
+
+  const int jt_beg = split * a.jt_chunk;
+  const int jt_end = jt_beg + a.jt_chunk < a.jt_count ? jt_beg + a.jt_chunk : a.jt_count;
+
+  float xi[RB][P];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int64_t i = rt * BM + wave * 16 * RB + rb * 16 + l16;
+#pragma unroll
+    for (int c = 0; c < P; ++c) xi[rb][c] = i < a.m ? a.Xq[i * P + c] : 0.0f;
+  }
+
+  f32x4 acc[G2][RB];
+  double tot[G2][RB][4];
+  float accv[G2][RB][NVa];
+  double totv[G2][RB][NVa];
+#pragma unroll
+  for (int g = 0; g < G2; ++g)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      acc[g][rb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tot[g][rb][r] = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        accv[g][rb][v] = 0.0f;
+        totv[g][rb][v] = 0.0;
+      }
+    }
+
+  constexpr int XC = kBJ * P / 4;
+  const int vchunks = vtile / 4;
+  auto gload = [&](int64_t jt, int buf) {
+    char* xs = reinterpret_cast<char*>(Xs + buf * kBJ * P);
+    char* vs = reinterpret_cast<char*>(Vs + buf * vtile);
+    const int64_t j0 = jt * kBJ;
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.Xp + j0 * P, (int64_t)kBJ * P * 4);
+    for (int m = wave * 64; m < XC; m += 256)
+      if (m + lane < XC)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_t*)(xs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.V + j0 * k, (a.nk_pad - j0 * k) * 4);
+    for (int m = wave * 64; m < vchunks; m += 256)
+      if (m + lane < vchunks)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, (lds_void_t*)(vs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
+  };
+
+  auto flush = [&]() {
+    const int64_t nk = a.m * k;
+    float* q1 = a.part + (int64_t)split * nk + rt * BM * k;
+    float* q2 = GRAD ? a.part2 + (int64_t)split * nk + rt * BM * k : nullptr;
+    const int64_t rows_left = a.m - rt * BM;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int lrow0 = wave * 16 * RB + rb * 16;
+      if (l16 < k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lrow = lrow0 + 4 * q + r;
+          if (lrow < rows_left) {
+            q1[lrow * k + l16] = (float)tot[0][rb][r];
+            if constexpr (GRAD) q2[lrow * k + l16] = (float)tot[G2 - 1][rb][r];
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G2; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[g][rb][r] = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        // lanes l16 + 16q hold the J points ≡ q (mod 4) of row l16
+#pragma unroll
+        for (int g = 0; g < G2; ++g) {
+          totv[g][rb][v] += __shfl_xor(totv[g][rb][v], 16);
+          totv[g][rb][v] += __shfl_xor(totv[g][rb][v], 32);
+        }
+        if (q == 0 && lrow0 + l16 < rows_left) {
+          q1[(lrow0 + l16) * k + 16 + v] = (float)totv[0][rb][v];
+          if constexpr (GRAD) q2[(lrow0 + l16) * k + 16 + v] = (float)totv[G2 - 1][rb][v];
+        }
+#pragma unroll
+        for (int g = 0; g < G2; ++g) totv[g][rb][v] = 0.0;
+      }
+    }
+  };
+
+  int cur = 0;
+  if (jt_beg < jt_end) gload(jt_beg, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int jt = jt_beg; jt < jt_end; ++jt) {
+    if (jt + 1 < jt_end) gload(jt + 1, cur ^ 1);
+
+    const float* xs = Xs + cur * kBJ * P + q * P;
+    const float* vb_base = Vs + cur * vtile + q * k + l16;
+    const float* vv_base = Vs + cur * vtile + q * k + 16;
+    const bool col_ok = EXACT || l16 < k;  // B columns beyond k are zero
+#pragma unroll 2
+    for (int st = 0; st < kBJ / 4; ++st) {
+      const float* xj = xs + st * 4 * P;
+      float kv[RB], kg[RB];
+      f32x4 xv[P / 4];
+#pragma unroll
+      for (int c4 = 0; c4 < P / 4; ++c4) xv[c4] = *reinterpret_cast<const f32x4*>(xj + 4 * c4);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        float r2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const float df = xi[rb][c] - xv[c >> 2][c & 3];
+          r2 = fmaf(df, df, r2);
+        }
+        kval_f32<KERN, GRAD>(r2, kv[rb], kg[rb]);
+      }
+      const int vo = st * 4 * k;
+      const float vb = col_ok ? vb_base[vo] : 0.0f;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        acc[0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rb], vb, acc[0][rb], 0, 0, 0);
+        if constexpr (GRAD)
+          acc[G2 - 1][rb] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(kg[rb], vb, acc[G2 - 1][rb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float vv = vv_base[vo + v];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          accv[0][rb][v] = fmaf(kv[rb], vv, accv[0][rb][v]);
+          if constexpr (GRAD) accv[G2 - 1][rb][v] = fmaf(kg[rb], vv, accv[G2 - 1][rb][v]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G2; ++g)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[g][rb][r] += (double)acc[g][rb][r];
+        acc[g][rb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          totv[g][rb][v] += (double)accv[g][rb][v];
+          accv[g][rb][v] = 0.0f;
+        }
+      }
+
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    cur ^= 1;
+  }
+  flush();
+}
+
 // out = f²·Σ_s P1[s] + s·V (chunks added in order, in FP64; V null: no
 // s·V term, as for a rectangular MatVec), and the derivative outputs.
 __global__ void kmv_f32_epilogue(const float* __restrict__ P1, const float* __restrict__ P2,
