@@ -24,19 +24,39 @@ struct BatchJob {
   int dcode;           // 2, 3, 4 or 8 (padded point dimension)
 };
 
-// Column kinds of a batched launch: 0 = k ≤ 32 through one 32-column MFMA
-// block; 1 / 2 = k = 1 / 2 on the VALU only (a CG-only round).  The VALU
-// kinds take four 32-row blocks per wave (more independent work per LDS read
-// of a point) and reserve LDS only for the columns they carry, so more
-// workgroups fit on a CU.
+// Column kinds of a batched launch: 0 = 18 ≤ k ≤ 32 through one 32-column
+// MFMA block; 1 / 2 = k = 1 / 2 on the VALU only (a CG-only round); 4 / 5 =
+// 3 ≤ k ≤ 16 / k = 17 through one 16-column MFMA block (+ one VALU column),
+// the Lanczos rounds of a request with 16 probes.  (Kind 3, the symmetric
+// block pairs, has its own kernel below.)  The VALU kinds take four 32-row
+// blocks per wave (more independent work per LDS read of a point) and
+// reserve LDS only for the columns they carry, so more workgroups fit on a
+// CU.
 template <int KIND> struct KindCols;
-template <> struct KindCols<0> { static constexpr int NB = 1, NV = 0, RB = 2, KMAX = 32; };
-template <> struct KindCols<1> { static constexpr int NB = 0, NV = 1, RB = 4, KMAX = 1; };
-template <> struct KindCols<2> { static constexpr int NB = 0, NV = 2, RB = 4, KMAX = 2; };
+template <> struct KindCols<0> {
+  static constexpr int NB = 1, NV = 0, RB = 2, KMAX = 32;
+  static constexpr bool W16 = false, EXACT = false;
+};
+template <> struct KindCols<1> {
+  static constexpr int NB = 0, NV = 1, RB = 4, KMAX = 1;
+  static constexpr bool W16 = false, EXACT = true;
+};
+template <> struct KindCols<2> {
+  static constexpr int NB = 0, NV = 2, RB = 4, KMAX = 2;
+  static constexpr bool W16 = false, EXACT = true;
+};
+template <> struct KindCols<4> {
+  static constexpr int NB = 0, NV = 0, RB = 4, KMAX = 16;
+  static constexpr bool W16 = true, EXACT = false;
+};
+template <> struct KindCols<5> {
+  static constexpr int NB = 0, NV = 1, RB = 4, KMAX = 17;
+  static constexpr bool W16 = true, EXACT = true;
+};
 
 template <int KIND>
 constexpr int64_t kind_rows() {  // rows per work unit
-  return 32LL * KindCols<KIND>::RB * kWaves;
+  return (KindCols<KIND>::W16 ? 16LL : 32LL) * KindCols<KIND>::RB * kWaves;
 }
 
 template <int KIND>
@@ -44,15 +64,23 @@ constexpr size_t kind_lds() {  // X tile (8 floats a point) + V tile, double-buf
   return (size_t)2 * kBJ * (8 + KindCols<KIND>::KMAX) * 4;
 }
 
+template <int KERN, int KIND, int D>
+__device__ __forceinline__ void batch_unit_d(const Args& a, int64_t rt, int split, float* smem) {
+  constexpr int NB = KindCols<KIND>::NB, NV = KindCols<KIND>::NV, RB = KindCols<KIND>::RB;
+  constexpr bool EX = KindCols<KIND>::EXACT;
+  if constexpr (KindCols<KIND>::W16)
+    kmv_f32_unit16<KERN, D, NV, RB, false, EX>(a, rt, split, smem);
+  else
+    kmv_f32_unit<KERN, D, NB, NV, RB, false, EX>(a, rt, split, smem);
+}
+
 template <int KERN, int KIND>
 __device__ __forceinline__ void batch_unit(const Args& a, int dcode, int64_t rt, int split,
                                            float* smem) {
-  constexpr int NB = KindCols<KIND>::NB, NV = KindCols<KIND>::NV, RB = KindCols<KIND>::RB;
-  constexpr bool EX = KIND != 0;  // k = 1 and k = 2 are exact
-  if (dcode == 2) kmv_f32_unit<KERN, 2, NB, NV, RB, false, EX>(a, rt, split, smem);
-  else if (dcode == 3) kmv_f32_unit<KERN, 3, NB, NV, RB, false, EX>(a, rt, split, smem);
-  else if (dcode == 4) kmv_f32_unit<KERN, 4, NB, NV, RB, false, EX>(a, rt, split, smem);
-  else kmv_f32_unit<KERN, 8, NB, NV, RB, false, EX>(a, rt, split, smem);
+  if (dcode == 2) batch_unit_d<KERN, KIND, 2>(a, rt, split, smem);
+  else if (dcode == 3) batch_unit_d<KERN, KIND, 3>(a, rt, split, smem);
+  else if (dcode == 4) batch_unit_d<KERN, KIND, 4>(a, rt, split, smem);
+  else batch_unit_d<KERN, KIND, 8>(a, rt, split, smem);
 }
 
 template <int KIND>
@@ -291,11 +319,14 @@ int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st,
 
 int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus) {
   if (count <= 0) return HIGP_OK;
-  std::vector<BatchJob> hj[3];
-  std::vector<const BatchMatvec*> src[3];
+  constexpr int kKinds = 6;  // kind 3 (symmetric) is collected separately
+  std::vector<BatchJob> hj[kKinds];
+  std::vector<const BatchMatvec*> src[kKinds];
   std::vector<const BatchMatvec*> sym;
-  int64_t total[3] = {0, 0, 0};
-  size_t part_elems[3] = {0, 0, 0};
+  int64_t total[kKinds] = {0, 0, 0, 0, 0, 0};
+  size_t part_elems[kKinds] = {0, 0, 0, 0, 0, 0};
+  const int64_t rows_of[kKinds] = {kind_rows<0>(), kind_rows<1>(), kind_rows<2>(), 0,
+                                   kind_rows<4>(), kind_rows<5>()};
   for (int i = 0; i < count; ++i) {
     const BatchMatvec& J = jobs[i];
     if (J.k < 1 || J.k > 32)
@@ -304,10 +335,10 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
       sym.push_back(&J);
       continue;
     }
-    const int kind = J.k == 1 ? 1 : (J.k == 2 ? 2 : 0);
+    const int kind = J.k == 1 ? 1 : J.k == 2 ? 2 : J.k <= 16 ? 4 : J.k == 17 ? 5 : 0;
     const int S = batch_splits(J.n);
     const int64_t jt = (J.n + kBJ - 1) / kBJ;
-    const int64_t bm = kind == 0 ? kind_rows<0>() : kind_rows<1>();
+    const int64_t bm = rows_of[kind];
     const int64_t rt = (J.n + bm - 1) / bm;
     BatchJob b{};
     b.a.Xp = J.Xp;
@@ -330,6 +361,8 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
   HIGP_TRY(launch_batch_kind<0>(hj[0], src[0], total[0], part_elems[0], st, num_cus));
   HIGP_TRY(launch_batch_kind<1>(hj[1], src[1], total[1], part_elems[1], st, num_cus));
   HIGP_TRY(launch_batch_kind<2>(hj[2], src[2], total[2], part_elems[2], st, num_cus));
+  HIGP_TRY(launch_batch_kind<4>(hj[4], src[4], total[4], part_elems[4], st, num_cus));
+  HIGP_TRY(launch_batch_kind<5>(hj[5], src[5], total[5], part_elems[5], st, num_cus));
   HIGP_TRY(launch_batch_sym(sym, st, num_cus));
   return HIGP_OK;
 }
