@@ -91,6 +91,9 @@ def main():
                          "paper, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
+    ap.add_argument("--serve-slots", type=int, default=8,
+                    help="max_active of the serving replays (concurrent requests; 8 gave the "
+                         "lowest p50 at full throughput in a sweep over 4-64)")
     ap.add_argument("--serve-rank", type=int, default=512,
                     help="Nyström rank of the second serving replay (0: skip it)")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
@@ -258,9 +261,10 @@ def main():
         for kname, kid in (("gaussian", 0), ("matern32", 1)):
             out["paper_shape_e2e_" + kname] = leg_paper_shape(kid)
     if "serve" in legs and args.serve > 0:
-        out["serving"] = leg_serve(args.serve)
+        out["serving"] = leg_serve(args.serve, slots=args.serve_slots)
         if args.serve_rank > 0:
-            out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank)
+            out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank,
+                                               slots=args.serve_slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
@@ -532,11 +536,12 @@ def leg_paper_shape(kernel):
                               "inference 1.76 s")
 
 
-def leg_serve(nreq, precond_rank=0):
+def leg_serve(nreq, precond_rank=0, slots=8):
     """Continuous batching: the first `nreq` requests of the Poisson stream
     (rate 200/s; n log-uniform in [1e3, 2e5]; d ∈ {2,3,8}; l ~ U[0.05,0.5];
     s = 1e-2; FP32), each CG to 1e-6 (Jacobi, or the Nyström preconditioner
-    of rank `precond_rank`) + SLQ 16 probes × 40 steps."""
+    of rank `precond_rank`) + SLQ 16 probes × 40 steps; at most `slots`
+    requests active at once."""
     import torch
     from paper_2503_02259_amd import workloads as W
     from paper_2503_02259_amd.serve import Server, replay
@@ -553,13 +558,13 @@ def leg_serve(nreq, precond_rank=0):
         stats.append((st.iters, st.converged, st.rounds))
         _log("serve: %d/%d done (request %d, %d CG iterations)" % (len(stats), nreq, i, st.iters))
 
-    srv = Server(hbm_budget=128 << 30, max_active=64)
+    srv = Server(hbm_budget=128 << 30, max_active=slots)
     r = replay(reqs, srv, upload, tol=1e-6, max_iter=1000, nsteps=40, on_done=done,
                precond_rank=precond_rank)
     srv.close()
     pc = "Nystrom rank %d" % precond_rank if precond_rank else "Jacobi"
-    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 (%s) + SLQ 16x40, FP32"
-                         % (nreq, pc),
+    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 (%s) + SLQ 16x40, FP32, "
+                         "%d slots" % (nreq, pc, slots), slots=slots,
                 requests=nreq, p50_s=r["p50"], p99_s=r["p99"], solves_per_s=r["throughput"],
                 span_s=r["span"], cg_iters_mean=float(np.mean([x[0] for x in stats])),
                 converged=int(sum(x[1] for x in stats)))
