@@ -91,6 +91,9 @@ def main():
                          "paper, serve) or 'none'")
     ap.add_argument("--serve", type=int, default=64, metavar="N",
                     help="requests of the serving stream to replay (the full stream has 512)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed headline MatVecs (no PCIe-inclusive or other-kernel "
+                         "MatVecs): the launches a profile of the headline kernel should see")
     ap.add_argument("--serve-slots", type=int, default=8,
                     help="max_active of the serving replays (concurrent requests; 8 gave the "
                          "lowest p50 at full throughput in a sweep over 4-64)")
@@ -178,6 +181,10 @@ def main():
                      "traffic": measured_traffic() if kern == hg.GAUSSIAN else None},
         "wall_s_timed": wall,
     }
+
+    if args.headline_only:
+        print(json.dumps(out))
+        return
 
     # The same MatVec when X and V start in (pinned) host memory and Y must go
     # back: the PCIe-inclusive rate, reported beside the HBM-resident value.
