@@ -348,7 +348,9 @@ int hutchpp_impl(const Problem& p, const void* y, int N, const void* Z, const hi
     const Cols q1 = view(at(o_qt), ns, 0, 0);
     if ((rc = gram(x, r1, q1, r1, q1))) return done(rc);
     const int r2 = orth_factor(r1, x.host, 0.0, C2);
-    if (r2 != r1) return done(set_error(HIGP_ERR_HIP, "Hutch++ sketch lost rank in re-orthogonalisation"));
+    if (r2 != r1)
+      return done(set_error(HIGP_ERR_UNSUPPORTED,
+                            "Hutch++: the sketch lost rank in its second orthonormalisation"));
     qoff[t] = rt;
     r[t] = r2;
     if ((rc = gemm(x, r1, q1, r2, C2, none, 1.0, view(at(o_b2), k2max, rt, 0)))) return done(rc);
