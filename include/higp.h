@@ -47,7 +47,7 @@ extern "C" {
 
 #define HIGP_OK 0
 #define HIGP_ERR_INVALID_ARG (-1) /* a size, pointer or parameter is out of range */
-#define HIGP_ERR_UNSUPPORTED (-2) /* a valid combination this build does not implement */
+#define HIGP_ERR_UNSUPPORTED (-2) /* a valid combination the library does not implement */
 #define HIGP_ERR_OOM (-3)         /* device scratch allocation failed */
 #define HIGP_ERR_HIP (-4)         /* a HIP runtime call failed (message has the detail) */
 
@@ -183,7 +183,7 @@ int higp_pcg(const higp_problem* p, int32_t k, const void* B, void* Xsol,
  * T = SΘSᵀ in FP64 on the host, and ‖z‖²·Σ_k S_{1k}²·log θ_k.
  * A probe stops early (shorter T) when β_j ≤ 1e-12·max_{i≤j}|α_i|.
  * Z: device n×nprobe probe block in the problem's precision (normally ±1).
- *    Z = NULL is not supported by this build (HIGP_ERR_UNSUPPORTED); pass
+ *    Z = NULL is not supported (HIGP_ERR_UNSUPPORTED); pass
  *    the probes explicitly.  `seed` is reserved and ignored.
  * logdet: host, receives log|M| + mean of the probes' quadratures.
  * per_probe: host array of nprobe (may be NULL): log|M| + each probe's value.
