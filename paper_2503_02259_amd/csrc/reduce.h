@@ -2,9 +2,10 @@
 //
 // A grid of G blocks covers the rows in fixed chunks.  Inside a block the 256
 // threads form cw = 2^⌈log₂k⌉ column lanes × 256/cw row lanes (so a single
-// column still uses every thread); the row lanes are summed by a fixed tree,
-// each block writes its per-column partial sums, and the last block to finish
-// (ticket counter) adds the G partials in block order.  The result depends
+// column still uses every thread); the row lanes of a wavefront are summed by
+// a fixed butterfly of lane shuffles, the four wavefronts' sums are added in
+// order through LDS, each block writes its per-column partial sums, and the
+// last block to finish (ticket counter) adds the G partials in block order.  The result depends
 // only on n and k, not on scheduling, so repeated runs and runs inside a
 // batch are bitwise equal.
 #pragma once
@@ -48,17 +49,21 @@ __device__ __forceinline__ ColLanes col_lanes(int k) {
 }
 
 // Block-level: sum `v` (this thread's partial for its column lane) over the
-// row lanes by a fixed tree; on return sh[c] (c < cw) holds column c's block
-// sum.  Must be called by all threads.  `sh` is 256 doubles of LDS.
+// row lanes; on return sh[c] (c < cw) holds column c's block sum.  Within a
+// wavefront the lanes of one column differ in lane bits lg..5, summed by an
+// XOR butterfly (fixed order); then the four wavefronts' sums are added in
+// wavefront order.  Must be called by all threads.  `sh` is 256 doubles of
+// LDS.
 __device__ __forceinline__ void block_colsum(double v, int k, double* sh) {
   const ColLanes L = col_lanes(k);
   const int tid = threadIdx.x;
-  sh[tid] = v;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int m = 32; m >= (1 << L.lg); m >>= 1) v += __shfl_xor(v, m);
+  __syncthreads();  // sh may still be read by a previous call
+  if (lane < (1 << L.lg)) sh[wave * 64 + lane] = v;
   __syncthreads();
-  for (int s = L.step >> 1; s > 0; s >>= 1) {
-    if (L.r0 < s) sh[tid] += sh[tid + (s << L.lg)];
-    __syncthreads();
-  }
+  if (tid < (1 << L.lg)) sh[tid] = ((sh[tid] + sh[64 + tid]) + sh[128 + tid]) + sh[192 + tid];
+  __syncthreads();
 }
 
 // Block sums as above, written to work[blockIdx.x*64 + c]; then the last
