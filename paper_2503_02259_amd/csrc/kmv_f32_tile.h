@@ -193,7 +193,7 @@ __device__ __forceinline__ void kmv_f32_unit(const Args& a, int64_t rt, int spli
     const float* xs = Xs + cur * kBJ * P + half * P;
     const float* vb_base = Vs + cur * vtile + half * k + l32;
     const float* vv_base = Vs + cur * vtile + half * k + NB * 32;
-#pragma unroll 2
+#pragma unroll 4
     for (int st = 0; st < kBJ / 2; ++st) {
       const float* xj = xs + st * 2 * P;
       float kv[RB], kg[RB];
