@@ -257,47 +257,55 @@ __global__ __launch_bounds__(256) void nys_tri_gemm(int64_t n, int r, const T* _
     }
 }
 
-// part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c]; block: 64 landmarks ×
-// 4 column groups, rows of R staged in LDS.
+// Row splits of WᵀR: enough blocks for several per CU (at k ≥ 4 a split has
+// ⌈r/64⌉ blocks) while each split keeps at least 512 rows.
+int wtr_splits(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(128, n / 512));
+}
+
+// part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c].  A block covers 256/CG
+// landmarks a and CG column groups; a thread adds the columns c ≡ cg (mod
+// CG), c < k, of its landmark (CG = 4 for k ≥ 4, else k), so that no FMA is
+// spent on absent columns.  Rows of R are staged in LDS kRI at a time.
 constexpr int kRI = 32;
-template <typename T>
+template <typename T, int CG>
 __global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T* __restrict__ W,
                                                const double* __restrict__ R, int64_t chunk,
                                                double* __restrict__ part) {
+  constexpr int NA = 256 / CG;  // landmarks per block
+  constexpr int QM = 64 / CG;   // most columns per thread
   __shared__ double rs[kRI][64];
-  const int la = threadIdx.x % 64, cg = threadIdx.x / 64;
-  const int a = blockIdx.x * 64 + la;
+  const int la = threadIdx.x % NA, cg = threadIdx.x / NA;
+  const int a = blockIdx.x * NA + la;
   const int s = blockIdx.y;
   const int64_t beg = (int64_t)s * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
-  double acc[16];
+  const int Q = (k - cg + CG - 1) / CG;  // this thread's columns
+  double acc[QM];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int q = 0; q < QM; ++q) acc[q] = 0.0;
   for (int64_t i0 = beg; i0 < end; i0 += kRI) {
-    for (int e = threadIdx.x; e < kRI * 64; e += 256) {
-      const int ii = e / 64, c = e % 64;
+    for (int e = threadIdx.x; e < kRI * k; e += 256) {
+      const int ii = e / k, c = e % k;
       const int64_t i = i0 + ii;
-      rs[ii][c] = (i < end && c < k) ? R[i * k + c] : 0.0;
+      rs[ii][c] = i < end ? R[i * k + c] : 0.0;
     }
     __syncthreads();
     const int rows = (int)std::min<int64_t>(kRI, end - i0);
     for (int ii = 0; ii < rows; ++ii) {
       const double w = a < r ? (double)W[(i0 + ii) * r + a] : 0.0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = fma(w, rs[ii][cg + 4 * q], acc[q]);
+      for (int q = 0; q < QM; ++q)
+        if (q < Q) acc[q] = fma(w, rs[ii][cg + CG * q], acc[q]);
     }
     __syncthreads();
   }
   if (a < r) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg + 4 * q;
-      if (c < k) part[((int64_t)s * r + a) * k + c] = acc[q];
-    }
+    for (int q = 0; q < QM; ++q)
+      if (q < Q) part[((int64_t)s * r + a) * k + cg + CG * q] = acc[q];
   }
 }
-
-// u[a][c] = Σ_b C⁻¹[a][b]·(Σ_s part[s][b][c]); T = Σ_s part is formed first.
 __global__ void nys_reduce_parts(int rk, int S, const double* __restrict__ part,
                                  double* __restrict__ Tm) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rk; e += gridDim.x * blockDim.x) {
@@ -320,41 +328,52 @@ __global__ void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
 
 // Z[i][c] = (R[i][c] − Σ_a W[i][a]·u[a][c]) / s.  Block: 64 rows × 4 column
 // groups; landmarks in chunks of 64 staged in LDS.
-template <typename T>
+// Z = (R − W·u)/s for an n×k block.  A block covers 256/CG rows and CG
+// column groups (as in nys_wtr); the landmark dimension is walked in chunks
+// of 16·CG, with the W and u chunks staged in LDS.
+template <typename T, int CG>
 __global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
                                                    const T* __restrict__ W,
                                                    const double* __restrict__ u,
                                                    const double* __restrict__ R, double inv_s,
                                                    double* __restrict__ Z) {
-  __shared__ double us[64][64];
-  __shared__ double ws[64][65];
-  const int lr = threadIdx.x % 64, cg = threadIdx.x / 64;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lr;
-  double acc[16];
+  constexpr int NR = 256 / CG;  // rows per block
+  constexpr int AC = 16 * CG;   // landmarks per LDS chunk
+  constexpr int QM = 64 / CG;
+  __shared__ double us[AC][64];
+  __shared__ double ws[NR][AC + 1];
+  const int lr = threadIdx.x % NR, cg = threadIdx.x / NR;
+  const int64_t i = (int64_t)blockIdx.x * NR + lr;
+  const int Q = (k - cg + CG - 1) / CG;
+  double acc[QM];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int a0 = 0; a0 < r; a0 += 64) {
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-      const int aa = e / 64, c = e % 64;
-      us[aa][c] = (a0 + aa < r && c < k) ? u[(a0 + aa) * k + c] : 0.0;
-      const int rr = e / 64, ac = e % 64;
-      const int64_t ir = (int64_t)blockIdx.x * 64 + rr;
+  for (int q = 0; q < QM; ++q) acc[q] = 0.0;
+  for (int a0 = 0; a0 < r; a0 += AC) {
+    for (int e = threadIdx.x; e < AC * k; e += 256) {
+      const int aa = e / k, c = e % k;
+      us[aa][c] = a0 + aa < r ? u[(a0 + aa) * k + c] : 0.0;
+    }
+    for (int e = threadIdx.x; e < NR * AC; e += 256) {
+      const int rr = e / AC, ac = e % AC;
+      const int64_t ir = (int64_t)blockIdx.x * NR + rr;
       ws[rr][ac] = (ir < n && a0 + ac < r) ? (double)W[ir * r + a0 + ac] : 0.0;
     }
     __syncthreads();
-    for (int aa = 0; aa < 64; ++aa) {
+    for (int aa = 0; aa < AC; ++aa) {
       const double w = ws[lr][aa];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = fma(w, us[aa][cg + 4 * q], acc[q]);
+      for (int q = 0; q < QM; ++q)
+        if (q < Q) acc[q] = fma(w, us[aa][cg + CG * q], acc[q]);
     }
     __syncthreads();
   }
   if (i < n) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg + 4 * q;
-      if (c < k) Z[i * k + c] = (R[i * k + c] - acc[q]) * inv_s;
-    }
+    for (int q = 0; q < QM; ++q)
+      if (q < Q) {
+        const int c = cg + CG * q;
+        Z[i * k + c] = (R[i * k + c] - acc[q]) * inv_s;
+      }
   }
 }
 
@@ -441,7 +460,7 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   const int64_t n = p.n;
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
   const int fps_blocks = (int)std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
-  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 4096));
+  const int S = wtr_splits(n);
   const int64_t chunk = (n + S - 1) / S;
   // Persistent part: L, C⁻¹, sel.  Work part (apply): partials, T, u.
   const size_t l_bytes = rup((size_t)n * r * sizeof(T));
@@ -557,16 +576,32 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
 
 template <typename T>
 int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
-  const int ab = (P.r + 63) / 64;
-  hipLaunchKernelGGL((nys_wtr<T>), dim3(ab, P.S), dim3(256), 0, st, P.n, P.r, k,
-                     static_cast<const T*>(P.W), R, P.chunk, P.part);
+  if (k >= 4)
+    hipLaunchKernelGGL((nys_wtr<T, 4>), dim3((P.r + 63) / 64, P.S), dim3(256), 0, st, P.n, P.r,
+                       k, static_cast<const T*>(P.W), R, P.chunk, P.part);
+  else if (k >= 2)
+    hipLaunchKernelGGL((nys_wtr<T, 2>), dim3((P.r + 127) / 128, P.S), dim3(256), 0, st, P.n,
+                       P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
+  else
+    hipLaunchKernelGGL((nys_wtr<T, 1>), dim3((P.r + 255) / 256, P.S), dim3(256), 0, st, P.n,
+                       P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
   const int rk = P.r * k;
   hipLaunchKernelGGL(nys_reduce_parts, dim3(grid_for(rk)), dim3(256), 0, st, rk, P.S,
                      (const double*)P.part, P.Tm);
   hipLaunchKernelGGL(nys_cinv_t, dim3(grid_for(rk)), dim3(256), 0, st, P.r, k,
                      (const double*)P.Cinv, (const double*)P.Tm, P.u);
-  hipLaunchKernelGGL((nys_apply_z<T>), dim3((unsigned)((P.n + 63) / 64)), dim3(256), 0, st, P.n,
-                     P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R, 1.0 / P.s, Z);
+  if (k >= 4)
+    hipLaunchKernelGGL((nys_apply_z<T, 4>), dim3((unsigned)((P.n + 63) / 64)), dim3(256), 0, st,
+                       P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R, 1.0 / P.s,
+                       Z);
+  else if (k >= 2)
+    hipLaunchKernelGGL((nys_apply_z<T, 2>), dim3((unsigned)((P.n + 127) / 128)), dim3(256), 0,
+                       st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
+                       1.0 / P.s, Z);
+  else
+    hipLaunchKernelGGL((nys_apply_z<T, 1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0,
+                       st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
+                       1.0 / P.s, Z);
   return hipGetLastError() == hipSuccess ? HIGP_OK
                                          : set_error(HIGP_ERR_HIP, "preconditioner apply failed");
 }
@@ -592,7 +627,7 @@ int nys_apply(const NysPrec& P, int k, const double* R, double* Z, hipStream_t s
 
 size_t nys_bytes(int64_t n, int rank, int kmax, int prec) {
   const int r = (int)std::min<int64_t>(rank, n);
-  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 4096));
+  const int S = wtr_splits(n);
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t es = prec == HIGP_FP64 ? 8 : 4;
   return rup((size_t)n * r * es) + rup((size_t)r * r * 8) + rup((size_t)r * 4) +
