@@ -24,6 +24,7 @@
 // chunk order, u = C⁻¹T, Z = (R − L·u)/s.  Everything is deterministic.
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "kvalue.h"
@@ -379,14 +380,47 @@ __global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
 
 // Lower Cholesky factor of the SPD matrix A (r×r, row-major; zeros above
 // the diagonal).  Returns false if A is not numerically positive definite.
+// Dot product with eight independent partial sums combined in a fixed order
+// (vectorisable, and the same result on every run).
+double dot8(const double* a, const double* b, int n) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 8 <= n; q += 8)
+    for (int t = 0; t < 8; ++t) s[t] += a[q + t] * b[q + t];
+  double tot = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  for (; q < n; ++q) tot += a[q] * b[q];
+  return tot;
+}
+
+// f(i) for i in [0, n) on the host's threads, in contiguous static chunks
+// (each output is computed by one thread, so results do not depend on the
+// thread count).
+template <typename F>
+void host_parallel_for(int n, F f) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (nt == 1 || n < 64) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> team;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    team.emplace_back([=, &f] {
+      for (int i = b; i < e; ++i) f(i);
+    });
+  }
+  for (auto& th : team) th.join();
+}
+
 bool chol_lower(const std::vector<double>& A, int r, std::vector<double>& L) {
   L.assign((size_t)r * r, 0.0);
   for (int i = 0; i < r; ++i) {
     const double* li = &L[(size_t)i * r];
     for (int j = 0; j <= i; ++j) {
       const double* lj = &L[(size_t)j * r];
-      double s = A[(size_t)i * r + j];
-      for (int q = 0; q < j; ++q) s -= li[q] * lj[q];
+      const double s = A[(size_t)i * r + j] - dot8(li, lj, j);
       if (i == j) {
         if (!(s > 0.0)) return false;
         L[(size_t)i * r + i] = std::sqrt(s);
@@ -402,16 +436,14 @@ bool chol_lower(const std::vector<double>& A, int r, std::vector<double>& L) {
 // (L⁻¹)[i][j] (so column j of L⁻¹ is contiguous), zeros elsewhere.
 void tri_inverse_t(const std::vector<double>& L, int r, std::vector<double>& Mt) {
   Mt.assign((size_t)r * r, 0.0);
-  for (int j = 0; j < r; ++j) {
+  host_parallel_for(r, [&](int j) {  // columns of L⁻¹ are independent
     double* mj = &Mt[(size_t)j * r];
     mj[j] = 1.0 / L[(size_t)j * r + j];
     for (int i = j + 1; i < r; ++i) {
       const double* li = &L[(size_t)i * r];
-      double s = 0.0;
-      for (int q = j; q < i; ++q) s += li[q] * mj[q];
-      mj[i] = -s / li[i];
+      mj[i] = -dot8(li + j, mj + j, i - j) / li[i];
     }
-  }
+  });
 }
 
 // In-place inverse of the SPD matrix A (r×r, row-major): A = LLᵀ,
@@ -421,16 +453,14 @@ bool spd_inverse(std::vector<double>& A, int r) {
   if (!chol_lower(A, r, L)) return false;
   tri_inverse_t(L, r, Mt);
   // A⁻¹[a][b] = Σ_{i ≥ max(a,b)} L⁻¹[i][a]·L⁻¹[i][b] = Σ_i Mt[a][i]·Mt[b][i].
-  for (int a = 0; a < r; ++a) {
+  host_parallel_for(r, [&](int a) {
     const double* ma = &Mt[(size_t)a * r];
     for (int b = 0; b <= a; ++b) {
-      const double* mb = &Mt[(size_t)b * r];
-      double s = 0.0;
-      for (int i = a; i < r; ++i) s += ma[i] * mb[i];
+      const double s = dot8(ma + a, &Mt[(size_t)b * r] + a, r - a);
       A[(size_t)a * r + b] = s;
       A[(size_t)b * r + a] = s;
     }
-  }
+  });
   return true;
 }
 
