@@ -88,18 +88,35 @@ __global__ __launch_bounds__(kThreads) void fps_step(int64_t n, int d, const T* 
   __syncthreads();
   if (ticket != gridDim.x - 1) return;
   __threadfence();
-  if (threadIdx.x == 0) {
-    double v = -1.0;
-    int64_t idx = 0;
-    for (unsigned b = 0; b < gridDim.x; ++b) {
-      const double vb = __hip_atomic_load(&bval[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int64_t ib = __hip_atomic_load(&bidx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (vb > v || (vb == v && ib < idx)) {
-        v = vb;
-        idx = ib;
+  // The last block: every thread takes the block winners b ≡ tid, then the
+  // same tree as above (the largest value, lowest index on ties: the result
+  // does not depend on the order of the comparisons).
+  double v = -1.0;
+  int64_t idx = 0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += kThreads) {
+    const double vb = __hip_atomic_load(&bval[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t ib = __hip_atomic_load(&bidx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (vb > v || (vb == v && ib < idx)) {
+      v = vb;
+      idx = ib;
+    }
+  }
+  sv[threadIdx.x] = v;
+  si[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double v2 = sv[threadIdx.x + s];
+      const int64_t i2 = si[threadIdx.x + s];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
       }
     }
-    sel[j] = (int)idx;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sel[j] = (int)si[0];
     *counter = 0u;
   }
 }
@@ -489,7 +506,7 @@ template <typename T>
 int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   const int64_t n = p.n;
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
-  const int fps_blocks = (int)std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
+  const int fps_blocks = (int)std::min<int64_t>(256, (n + kThreads - 1) / kThreads);
   const int S = wtr_splits(n);
   const int64_t chunk = (n + S - 1) / S;
   // Persistent part: L, C⁻¹, sel.  Work part (apply): partials, T, u.
@@ -666,7 +683,7 @@ size_t nys_bytes(int64_t n, int rank, int kmax, int prec) {
 
 int fps_landmarks(const Problem& p, int rank, int* sel_host, hipStream_t st) {
   const int r = (int)std::min<int64_t>(rank, p.n);
-  const int blocks = (int)std::min<int64_t>(1024, (p.n + kThreads - 1) / kThreads);
+  const int blocks = (int)std::min<int64_t>(256, (p.n + kThreads - 1) / kThreads);
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t bytes = rup((size_t)r * 4) + rup((size_t)p.n * 8) + rup((size_t)blocks * 16) + 256;
   void* mem = nullptr;
