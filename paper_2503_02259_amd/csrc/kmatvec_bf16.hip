@@ -37,6 +37,7 @@
 #include <mutex>
 #include <unordered_map>
 
+#include "bufload.h"
 #include "kvalue.h"
 #include "reduce.h"
 
@@ -48,12 +49,6 @@ constexpr int kBJ = 128;       // J points per tile
 constexpr float kFarSq = 1e30f;  // squared norm of a sentinel point: exp2 → 0
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
-  const int nrec = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
-}
 
 // Column means of X (n×d) → ctr[0..d), summed in FP64 in a fixed order.
 __global__ __launch_bounds__(kRedThreads) void point_mean(int64_t n, int d, int64_t chunk,

@@ -9,6 +9,7 @@
 // order by an epilogue kernel (deterministic, no atomics).
 #include <algorithm>
 
+#include "bufload.h"
 #include "kvalue.h"
 
 namespace higp {
@@ -18,9 +19,9 @@ constexpr int kWaves = 4;
 
 template <typename T>
 struct KArgs {
-  const T* X;   // n×d row-major: the J (column) points
-  const T* Xq;  // m×d row-major: the row points (X for a square MatVec)
-  const T* V;   // n×k row-major
+  const T* Xp;  // npad×P prepared J (column) points: x·xs, rows ≥ n far-away sentinels
+  const T* Xq;  // m×d row-major: the row points (X for a square MatVec), unscaled
+  const T* V;   // n×k row-major, 16-byte aligned, readable up to nk_pad elements
   const T* sV;  // V for the s·V term (null for a rectangular MatVec)
   T* o1;        // S==1: K̂V (or null); S>1: partial Σ k·v, S×m×k
   T* o2;        // S==1: ∂K̂/∂l·V (or null); S>1: partial Σ k_l·v (GRAD only)
@@ -28,11 +29,41 @@ struct KArgs {
   int64_t n;    // J points
   int64_t m;    // rows
   int64_t jchunk;  // J points per split (multiple of the J tile)
+  int64_t nk_pad;  // readable elements of V (n·k rounded up to whole 16-byte chunks)
   int k, d, nsplit;
   T xs;          // coordinate pre-scale
   T f2, s;       // K̂ = f²K + sI (epilogue, S==1)
   T cl, cf;      // ∂K̂/∂l = cl·Σk_l v, ∂K̂/∂f = cf·Σk v (epilogue, S==1)
 };
+
+constexpr double kFar64 = 1e18;  // squared distance ~1e36: exp underflows to exactly 0
+
+// Padded storage width of an FP64 point with D coordinates (32-byte rows for
+// D ≤ 4, then multiples of 4 doubles).
+__host__ __device__ constexpr int pad_dim64(int d) {
+  return d <= 4 ? 4 : (d <= 8 ? 8 : (d + 3) / 4 * 4);
+}
+
+// a1: x̃ = x·xs padded to P doubles; rows n..npad−1 are far-away sentinels.
+__global__ void prep_points_f64(int64_t n, int64_t npad, int d, int P,
+                                const double* __restrict__ X, double xs,
+                                double* __restrict__ Xp) {
+  const int64_t count = npad * P;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / P;
+    const int c = (int)(e % P);
+    Xp[e] = i >= n ? kFar64 : (c < d ? X[i * d + c] * xs : 0.0);
+  }
+}
+
+// dst[0..count_pad) = src[0..count) followed by zeros.
+__global__ void copy_pad_f64(int64_t count, int64_t count_pad, const double* __restrict__ src,
+                             double* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count_pad;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = e < count ? src[e] : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // FP64: v_mfma_f64_16x16x4f64.  A wave owns 16 rows; per MFMA each lane
@@ -41,16 +72,21 @@ struct KArgs {
 // column l%16.  With NV = 1 one more column (k = 16·NB + 1, e.g. y plus 16
 // or 32 probes) is carried on the VALU: each lane adds its kernel values
 // times that column's V, and the 4 lanes of a row are added at the end.
+// J tiles of the prepared points and of V are copied global → LDS directly
+// (16-byte buffer loads, double-buffered); reads past the end of V return 0
+// and the prepared points past n are far away, so a ragged last tile needs
+// no branches.  EXACT instances have k = 16·NB + NV, a compile-time V row
+// stride.
 
 constexpr int kBJ64 = 64;  // J points per LDS tile (FP64 kernel)
 
-template <int KERN, int D, int NB, int NV, bool GRAD>
+template <int KERN, int D, int NB, int NV, bool GRAD, bool EXACT>
 __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
-  constexpr int P = D <= 4 ? 4 : (D <= 8 ? 8 : (D + 3) / 4 * 4);
+  constexpr int P = pad_dim64(D);
   constexpr int VC = NB * 16 + NV;
   constexpr int BM = 16 * kWaves;
-  __shared__ double Xs[2][kBJ64][P];
-  __shared__ double Vs[2][kBJ64][VC];
+  __shared__ __attribute__((aligned(16))) double Xs[2][kBJ64 * P];
+  __shared__ __attribute__((aligned(16))) double Vs[2][kBJ64 * VC];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -61,7 +97,8 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   const int64_t row0 = (int64_t)(blockIdx.x / a.nsplit) * BM;
   const int64_t jbeg = (int64_t)split * a.jchunk;
   const int64_t jend = min(a.n, jbeg + a.jchunk);
-  const int k = a.k, d = a.d;
+  const int k = EXACT ? VC : a.k;  // V row stride in LDS
+  const int d = a.d;
 
   const int64_t irow = row0 + wave * 16 + l16;
   double xi[D];
@@ -78,87 +115,61 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
   }
   double accx = 0.0, accx2 = 0.0;  // the VALU column (NV = 1)
 
-  constexpr int XPER = (kBJ64 * D + 255) / 256;
-  constexpr int VROWS = kBJ64 / 4;
-  double xr[XPER];
-  double vr[VROWS];
-  const int vc = tid & 63;
-  const int vr0 = tid >> 6;
-
-  auto gload = [&](int64_t jt) {
-#pragma unroll
-    for (int m = 0; m < XPER; ++m) {
-      const int e = tid + 256 * m;
-      const int r = e / D, c = e % D;
-      double v = 0.0;
-      if (e < kBJ64 * D && c < d && jt + r < jend) v = a.X[(jt + r) * d + c];
-      xr[m] = v;
-    }
-#pragma unroll
-    for (int m = 0; m < VROWS; ++m) {
-      const int64_t j = jt + vr0 + 4 * m;
-      double v = 0.0;
-      if (vc < k && j < jend) v = a.V[j * k + vc];
-      vr[m] = v;
-    }
+  // Every wave issues its share of 16-byte chunks, 64 consecutive chunks
+  // (1 KB) per instruction.
+  constexpr int XC = kBJ64 * P / 2;  // chunks of the X tile
+  const int vchunks = kBJ64 * k / 2;  // chunks of the V tile (k·64 doubles)
+  auto gload = [&](int64_t j0, int buf) {
+    char* xs = reinterpret_cast<char*>(&Xs[buf][0]);
+    char* vs = reinterpret_cast<char*>(&Vs[buf][0]);
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.Xp + j0 * P, (int64_t)kBJ64 * P * 8);
+    for (int m = wave * 64; m < XC; m += 256)
+      if (m + lane < XC)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_t*)(xs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.V + j0 * k, (a.nk_pad - j0 * k) * 8);
+    for (int m = wave * 64; m < vchunks; m += 256)
+      if (m + lane < vchunks)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, (lds_void_t*)(vs + 16 * m), 16,
+                                                 16 * (m + lane), 0, 0, 0);
   };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int m = 0; m < XPER; ++m) {
-      const int e = tid + 256 * m;
-      if (e < kBJ64 * D) Xs[buf][e / D][e % D] = xr[m] * a.xs;
-    }
-    if (vc < VC) {
-#pragma unroll
-      for (int m = 0; m < VROWS; ++m) Vs[buf][vr0 + 4 * m][vc] = vr[m];
-    }
-  };
-
-  if constexpr (P > D) {
-    for (int e = tid; e < 2 * kBJ64 * (P - D); e += 256) {
-      const int buf = e / (kBJ64 * (P - D));
-      const int rem = e % (kBJ64 * (P - D));
-      Xs[buf][rem / (P - D)][D + rem % (P - D)] = 0.0;
-    }
-  }
 
   const int64_t ntiles = (jend > jbeg) ? (jend - jbeg + kBJ64 - 1) / kBJ64 : 0;
-  if (ntiles > 0) {
-    gload(jbeg);
-    lstore(0);
-  }
+  if (ntiles > 0) gload(jbeg, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
   for (int64_t t = 0; t < ntiles; ++t) {
     const int cur = (int)(t & 1);
-    const bool more = t + 1 < ntiles;
-    if (more) gload(jbeg + (t + 1) * kBJ64);
+    if (t + 1 < ntiles) gload(jbeg + (t + 1) * kBJ64, cur ^ 1);
 
+    const double* xs = &Xs[cur][0];
+    const double* vs = &Vs[cur][0];
 #pragma unroll 2
     for (int st = 0; st < kBJ64 / 4; ++st) {
       const int j = 4 * st + q;
       double r2 = 0.0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double df = xi[c] - Xs[cur][j][c];
+        const double df = xi[c] - xs[j * P + c];
         r2 = fma(df, df, r2);
       }
       double kv, kg;
       kval_f64<KERN, GRAD>(r2, kv, kg);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const double vb = Vs[cur][j][b * 16 + l16];
+        const double vb = vs[j * k + b * 16 + l16];
         acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, vb, acc[b], 0, 0, 0);
         if constexpr (GRAD) acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kg, vb, acc2[b], 0, 0, 0);
       }
       if constexpr (NV == 1) {
-        const double vx = Vs[cur][j][NB * 16];
+        const double vx = vs[j * k + NB * 16];
         accx = fma(kv, vx, accx);
         if constexpr (GRAD) accx2 = fma(kg, vx, accx2);
       }
     }
 
-    if (more) lstore(cur ^ 1);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
@@ -244,24 +255,35 @@ using KFn = void (*)(KArgs<T>);
 
 template <int KERN, int D, bool GRAD>
 KFn<double> pick_f64_cols(int k) {
-  if (k <= 16) return kmv_f64<KERN, D, 1, 0, GRAD>;
-  if (k == 17) return kmv_f64<KERN, D, 1, 1, GRAD>;
-  if (k <= 32) return kmv_f64<KERN, D, 2, 0, GRAD>;
-  if (k == 33) return kmv_f64<KERN, D, 2, 1, GRAD>;
-  if (k <= 48) return kmv_f64<KERN, D, 3, 0, GRAD>;
-  if (k == 49) return kmv_f64<KERN, D, 3, 1, GRAD>;
-  return kmv_f64<KERN, D, 4, 0, GRAD>;
+  if (k < 16) return kmv_f64<KERN, D, 1, 0, GRAD, false>;
+  if (k == 16) return kmv_f64<KERN, D, 1, 0, GRAD, true>;
+  if (k == 17) return kmv_f64<KERN, D, 1, 1, GRAD, true>;
+  if (k < 32) return kmv_f64<KERN, D, 2, 0, GRAD, false>;
+  if (k == 32) return kmv_f64<KERN, D, 2, 0, GRAD, true>;
+  if (k == 33) return kmv_f64<KERN, D, 2, 1, GRAD, true>;
+  if (k < 48) return kmv_f64<KERN, D, 3, 0, GRAD, false>;
+  if (k == 48) return kmv_f64<KERN, D, 3, 0, GRAD, true>;
+  if (k == 49) return kmv_f64<KERN, D, 3, 1, GRAD, true>;
+  if (k < 64) return kmv_f64<KERN, D, 4, 0, GRAD, false>;
+  return kmv_f64<KERN, D, 4, 0, GRAD, true>;
+}
+
+// Compile-time dimension of the instance serving d coordinates.
+int f64_dim_code(int d) {
+  return d <= 2 ? 2 : d == 3 ? 3 : d == 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 20 ? 20 : 32;
 }
 
 template <int KERN, bool GRAD>
 KFn<double> pick_f64_d(int d, int k) {
-  if (d <= 2) return pick_f64_cols<KERN, 2, GRAD>(k);
-  if (d == 3) return pick_f64_cols<KERN, 3, GRAD>(k);
-  if (d == 4) return pick_f64_cols<KERN, 4, GRAD>(k);
-  if (d <= 8) return pick_f64_cols<KERN, 8, GRAD>(k);
-  if (d <= 16) return pick_f64_cols<KERN, 16, GRAD>(k);
-  if (d <= 20) return pick_f64_cols<KERN, 20, GRAD>(k);
-  return pick_f64_cols<KERN, 32, GRAD>(k);
+  switch (f64_dim_code(d)) {
+    case 2: return pick_f64_cols<KERN, 2, GRAD>(k);
+    case 3: return pick_f64_cols<KERN, 3, GRAD>(k);
+    case 4: return pick_f64_cols<KERN, 4, GRAD>(k);
+    case 8: return pick_f64_cols<KERN, 8, GRAD>(k);
+    case 16: return pick_f64_cols<KERN, 16, GRAD>(k);
+    case 20: return pick_f64_cols<KERN, 20, GRAD>(k);
+    default: return pick_f64_cols<KERN, 32, GRAD>(k);
+  }
 }
 
 // Number of J splits S (a power of two ≤ 64) so that the grid has at least
@@ -292,11 +314,10 @@ int run_f64(const Problem& p, int64_t m, const double* Xq, int k, const void* V,
   const bool grad = out.dl != nullptr || out.df != nullptr;
   const bool cross = Xq != nullptr;
   const int64_t rows = cross ? m : p.n;
+  const int P = pad_dim64(f64_dim_code(p.d));  // the instance's padded width
   KArgs<double> a{};
-  a.X = static_cast<const double*>(p.X);
-  a.Xq = cross ? Xq : a.X;
-  a.V = static_cast<const double*>(V);
-  a.sV = cross ? nullptr : a.V;
+  a.Xq = cross ? Xq : static_cast<const double*>(p.X);
+  a.sV = cross ? nullptr : static_cast<const double*>(V);
   a.n = p.n;
   a.m = rows;
   a.k = k;
@@ -310,17 +331,45 @@ int run_f64(const Problem& p, int64_t m, const double* Xq, int k, const void* V,
   a.nsplit = S;
   const int64_t tiles_j = (p.n + kBJ64 - 1) / kBJ64;
   a.jchunk = ((tiles_j + S - 1) / S) * kBJ64;
+  const int64_t npad = tiles_j * kBJ64;
   const int64_t nblocks = ((rows + bm - 1) / bm) * S;
+  if (nblocks > 0x7fffffffLL) return set_error(HIGP_ERR_INVALID_ARG, "n too large");
+  // Scratch: prepared points (whole J tiles); a zero-padded copy of V unless
+  // V is 16-byte aligned and n·k is even (tiles move 16-byte chunks); the
+  // split partials.
+  const int64_t nk = p.n * k;
+  const bool direct_v = (reinterpret_cast<uintptr_t>(V) & 15) == 0 && nk % 2 == 0;
+  const int64_t nk_pad = (nk + 1) / 2 * 2;
+  auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t xp_bytes = rup((size_t)npad * P * 8);
+  const size_t v_bytes = direct_v ? 0 : rup((size_t)nk_pad * 8);
+  const size_t per = S > 1 ? rup((size_t)rows * k * sizeof(double) * S) : 0;
   void* scratch = nullptr;
+  HIGP_TRY(scratch_alloc(&scratch, xp_bytes + v_bytes + per * (grad ? 2 : 1), st));
+  char* base = static_cast<char*>(scratch);
+  double* Xp = reinterpret_cast<double*>(base);
+  a.Xp = Xp;
+  a.V = static_cast<const double*>(V);
+  a.nk_pad = direct_v ? nk : nk_pad;
+  if (!direct_v) {
+    double* Vc = reinterpret_cast<double*>(base + xp_bytes);
+    const unsigned cb = (unsigned)std::min<int64_t>((nk_pad + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_pad_f64, dim3(cb), dim3(256), 0, st, nk, nk_pad,
+                       static_cast<const double*>(V), Vc);
+    a.V = Vc;
+  }
+  {
+    const unsigned pb = (unsigned)std::min<int64_t>((npad * P + 255) / 256, 4096);
+    hipLaunchKernelGGL(prep_points_f64, dim3(pb), dim3(256), 0, st, p.n, npad, p.d, P,
+                       static_cast<const double*>(p.X), xs, Xp);
+  }
   if (S == 1) {
     a.o1 = static_cast<double*>(out.kv);
     a.o2 = static_cast<double*>(out.dl);
     a.o3 = static_cast<double*>(out.df);
   } else {
-    const size_t per = (size_t)rows * k * sizeof(double) * S;
-    HIGP_TRY(scratch_alloc(&scratch, per * (grad ? 2 : 1), st));
-    a.o1 = static_cast<double*>(scratch);
-    a.o2 = grad ? reinterpret_cast<double*>(static_cast<char*>(scratch) + per) : nullptr;
+    a.o1 = reinterpret_cast<double*>(base + xp_bytes + v_bytes);
+    a.o2 = grad ? reinterpret_cast<double*>(base + xp_bytes + v_bytes + per) : nullptr;
   }
   hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(256), 0, st, a);
   int rc = hipGetLastError() == hipSuccess ? HIGP_OK
@@ -328,10 +377,9 @@ int run_f64(const Problem& p, int64_t m, const double* Xq, int k, const void* V,
   if (rc == HIGP_OK && S > 1)
     rc = launch_epilogue<double>(a.o1, grad ? a.o2 : nullptr, a.sV, out, rows * k, S, p.f * p.f,
                                  a.s, cl, 2.0 * p.f, st, num_cus);
-  if (scratch) scratch_free(scratch, st);
+  scratch_free(scratch, st);
   return rc;
 }
-
 
 }  // namespace
 

@@ -4,6 +4,7 @@
 // kmatvec_f32.hip for the design.
 #pragma once
 
+#include "bufload.h"
 #include "kvalue.h"
 
 namespace higp {
@@ -13,8 +14,6 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kBJ = 128;       // J points per LDS tile
 constexpr float kFar = 1e18f;  // squared distance ~1e36: exp2 underflows to exactly 0
-
-typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Padded storage width of a point with D coordinates: 4, 8, or D rounded up
 // to a multiple of 4 (16-byte loads).
@@ -45,12 +44,6 @@ __global__ void copy_pad_f32(int64_t count, int64_t count_pad, const float* __re
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count_pad;
        e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = e < count ? src[e] : 0.0f;
-}
-
-// Buffer resource over `bytes` bytes at `base` (reads past the end return 0).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
-  const int nrec = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
 }
 
 struct Args {
