@@ -281,10 +281,12 @@ int wtr_splits(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(128, n / 512));
 }
 
+// The apply's two passes for k ≤ 3 on the VALU (wider blocks take the MFMA
+// forms below).
 // part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c].  A block covers 256/CG
 // landmarks a and CG column groups; a thread adds the columns c ≡ cg (mod
-// CG), c < k, of its landmark (CG = 4 for k ≥ 4, else k), so that no FMA is
-// spent on absent columns.  Rows of R are staged in LDS kRI at a time.
+// CG), c < k, of its landmark (CG = k), so that no FMA is spent on absent
+// columns.  Rows of R are staged in LDS kRI at a time.
 constexpr int kRI = 32;
 template <typename T, int CG>
 __global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T* __restrict__ W,
@@ -344,8 +346,6 @@ __global__ void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
   }
 }
 
-// Z[i][c] = (R[i][c] − Σ_a W[i][a]·u[a][c]) / s.  Block: 64 rows × 4 column
-// groups; landmarks in chunks of 64 staged in LDS.
 // Z = (R − W·u)/s for an n×k block.  A block covers 256/CG rows and CG
 // column groups (as in nys_wtr); the landmark dimension is walked in chunks
 // of 16·CG, with the W and u chunks staged in LDS.
@@ -392,6 +392,136 @@ __global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
         const int c = cg + CG * q;
         Z[i * k + c] = (R[i * k + c] - acc[q]) * inv_s;
       }
+  }
+}
+
+// The same two passes for k ≥ 4 on v_mfma_f64_16x16x4f64 (NB blocks of 16
+// columns; lane layout: A[m][kk] from lane kk·16 + m, B[kk][c] from lane
+// kk·16 + c, result register e of lane l is C[l/16 + 4e][l%16]).
+//
+// part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c]: A = Wᵀ (16 landmarks ×
+// 4 rows), B = R (4 rows × 16 columns).  A wave covers 64 landmarks as 4
+// MFMA tiles (tile t: landmarks a0 + 16t + m) and walks its chunk 4 rows at a
+// time, the next group's loads issued before the current group's MFMAs.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void nys_wtr_mfma(int64_t n, int r, int k,
+                                                    const T* __restrict__ W,
+                                                    const double* __restrict__ R, int64_t chunk,
+                                                    double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int a0 = (blockIdx.x * 4 + wave) * 64;
+  if (a0 >= r) return;
+  const int s = blockIdx.y;
+  const int64_t beg = (int64_t)s * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  f64x4 acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[t][b] = f64x4{0};
+  auto load = [&](int64_t i0, double (&w)[4], double (&v)[NB]) {
+    const int64_t i = i0 + q;
+    const bool ok = i < end;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int a = a0 + 16 * t + m;
+      w[t] = ok && a < r ? (double)W[i * r + a] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = 16 * b + m;
+      v[b] = ok && c < k ? R[i * k + c] : 0.0;
+    }
+  };
+  double w[4], v[NB];
+  if (beg < end) load(beg, w, v);
+  for (int64_t i0 = beg; i0 < end; i0 += 4) {
+    double wn[4], vn[NB];
+    if (i0 + 4 < end) load(i0 + 4, wn, vn);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        acc[t][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[t], v[b], acc[t][b], 0, 0, 0);
+    if (i0 + 4 < end) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = wn[t];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[b] = vn[b];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = 16 * b + m;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int a = a0 + 16 * t + q + 4 * e;
+        if (a < r && c < k) part[((int64_t)s * r + a) * k + c] = acc[t][b][e];
+      }
+    }
+}
+
+// Z = (R − W·u)/s: A = W (16 rows × 4 landmarks), B = u (4 landmarks × 16
+// columns).  A wave owns 16 rows and walks the landmarks 16 at a time: lane
+// (q, m) loads landmarks a0 + 4q .. a0 + 4q + 3 of row m, and step t takes
+// landmark a0 + 4q + t as its reduction index q.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void nys_apply_z_mfma(int64_t n, int r, int k,
+                                                        const T* __restrict__ W,
+                                                        const double* __restrict__ u,
+                                                        const double* __restrict__ R,
+                                                        double inv_s, double* __restrict__ Z) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (i0 >= n) return;
+  const int64_t i = i0 + m;  // the row this lane loads
+  f64x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = f64x4{0};
+  auto load = [&](int a0, double (&w)[4], double (&v)[4][NB]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int a = a0 + 4 * q + t;
+      const bool ok = a < r;
+      w[t] = ok && i < n ? (double)W[i * r + a] : 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c = 16 * b + m;
+        v[t][b] = ok && c < k ? u[(int64_t)a * k + c] : 0.0;
+      }
+    }
+  };
+  double w[4], v[4][NB];
+  load(0, w, v);
+  for (int a0 = 0; a0 < r; a0 += 16) {
+    double wn[4], vn[4][NB];
+    if (a0 + 16 < r) load(a0 + 16, wn, vn);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[t], v[t][b], acc[b], 0, 0, 0);
+    if (a0 + 16 < r) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        w[t] = wn[t];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[t][b] = vn[t][b];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int c = 16 * b + m;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = i0 + q + 4 * e;
+      if (row < n && c < k) Z[row * k + c] = (R[row * k + c] - acc[b][e]) * inv_s;
+    }
   }
 }
 
@@ -621,34 +751,55 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   return HIGP_OK;
 }
 
+template <typename T, int NB>
+void launch_wtr_mfma(const NysPrec& P, int k, const double* R, hipStream_t st) {
+  hipLaunchKernelGGL((nys_wtr_mfma<T, NB>), dim3((P.r + 255) / 256, P.S), dim3(256), 0, st, P.n,
+                     P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
+}
+
+template <typename T, int NB>
+void launch_apply_z_mfma(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
+  hipLaunchKernelGGL((nys_apply_z_mfma<T, NB>), dim3((unsigned)((P.n + 63) / 64)), dim3(256), 0,
+                     st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
+                     1.0 / P.s, Z);
+}
+
 template <typename T>
 int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
-  if (k >= 4)
-    hipLaunchKernelGGL((nys_wtr<T, 4>), dim3((P.r + 63) / 64, P.S), dim3(256), 0, st, P.n, P.r,
-                       k, static_cast<const T*>(P.W), R, P.chunk, P.part);
-  else if (k >= 2)
+  // k ≥ 4: FP64 MFMA passes (NB = ⌈k/16⌉ blocks of 16 columns); k ≤ 3: the
+  // VALU passes, which spend no work on absent columns.
+  const int nb = (k + 15) / 16;
+  if (k >= 4) {
+    if (nb == 1) launch_wtr_mfma<T, 1>(P, k, R, st);
+    else if (nb == 2) launch_wtr_mfma<T, 2>(P, k, R, st);
+    else if (nb == 3) launch_wtr_mfma<T, 3>(P, k, R, st);
+    else launch_wtr_mfma<T, 4>(P, k, R, st);
+  } else if (k >= 2) {
     hipLaunchKernelGGL((nys_wtr<T, 2>), dim3((P.r + 127) / 128, P.S), dim3(256), 0, st, P.n,
                        P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
-  else
+  } else {
     hipLaunchKernelGGL((nys_wtr<T, 1>), dim3((P.r + 255) / 256, P.S), dim3(256), 0, st, P.n,
                        P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
+  }
   const int rk = P.r * k;
   hipLaunchKernelGGL(nys_reduce_parts, dim3(grid_for(rk)), dim3(256), 0, st, rk, P.S,
                      (const double*)P.part, P.Tm);
   hipLaunchKernelGGL(nys_cinv_t, dim3(grid_for(rk)), dim3(256), 0, st, P.r, k,
                      (const double*)P.Cinv, (const double*)P.Tm, P.u);
-  if (k >= 4)
-    hipLaunchKernelGGL((nys_apply_z<T, 4>), dim3((unsigned)((P.n + 63) / 64)), dim3(256), 0, st,
-                       P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R, 1.0 / P.s,
-                       Z);
-  else if (k >= 2)
+  if (k >= 4) {
+    if (nb == 1) launch_apply_z_mfma<T, 1>(P, k, R, Z, st);
+    else if (nb == 2) launch_apply_z_mfma<T, 2>(P, k, R, Z, st);
+    else if (nb == 3) launch_apply_z_mfma<T, 3>(P, k, R, Z, st);
+    else launch_apply_z_mfma<T, 4>(P, k, R, Z, st);
+  } else if (k >= 2) {
     hipLaunchKernelGGL((nys_apply_z<T, 2>), dim3((unsigned)((P.n + 127) / 128)), dim3(256), 0,
                        st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
                        1.0 / P.s, Z);
-  else
+  } else {
     hipLaunchKernelGGL((nys_apply_z<T, 1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0,
                        st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
                        1.0 / P.s, Z);
+  }
   return hipGetLastError() == hipSuccess ? HIGP_OK
                                          : set_error(HIGP_ERR_HIP, "preconditioner apply failed");
 }
