@@ -81,25 +81,33 @@ def round_bf16(a):
     return np.ldexp(np.round(m * 256.0), e - 8)   # np.round: half to even
 
 
-def kmatvec_bf16_emulated(X, V, kernel, l, f, s, block=512, workers=1):
+def _out_rows(n, rows):
+    """The output rows (a slice of range(n)) and their offset in the result."""
+    sel = slice(0, n) if rows is None else slice(*rows.indices(n)[:2])
+    return sel, sel.start
+
+
+def kmatvec_bf16_emulated(X, V, kernel, l, f, s, block=512, workers=1, rows=None):
     """The BF16 form of the MatVec, emulated: the kernel tile k(X, X; l) and
     V are each rounded to bfloat16 (round to nearest even), their products
     are exact and summed in float64; then Y = f²·acc + s·V with V unrounded.
+    ``rows`` (a slice, default all) restricts the output to those rows.
 
     This predicts the behaviour of a K-tile×V product done in BF16 with wide
     accumulation; it is not a pin of the FP64 result.
     """
     X = np.asarray(X, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
-    n = X.shape[0]
+    sel, off = _out_rows(X.shape[0], rows)
     Vb = round_bf16(V)
-    Y = np.empty_like(V)
+    Y = np.empty((sel.stop - sel.start,) + V.shape[1:])
 
-    def one(rows):
-        Kb = round_bf16(kernel_value(sqdist(X[rows], X), kernel, l))
-        Y[rows] = (f * f) * (Kb @ Vb) + s * V[rows]
+    def one(b):
+        r = slice(b.start + off, b.stop + off)
+        Kb = round_bf16(kernel_value(sqdist(X[r], X), kernel, l))
+        Y[b] = (f * f) * (Kb @ Vb) + s * V[r]
 
-    _run_blocks(one, n, block, workers)
+    _run_blocks(one, sel.stop - sel.start, block, workers)
     return Y
 
 
@@ -111,7 +119,7 @@ def split_bf16(a):
     return hi, round_bf16(np.asarray(a, dtype=np.float64) - hi)
 
 
-def kmatvec_bf16x3_emulated(X, V, kernel, l, f, s, block=512, workers=1):
+def kmatvec_bf16x3_emulated(X, V, kernel, l, f, s, block=512, workers=1, rows=None):
     """The split-BF16 form of the MatVec, emulated: the kernel tile K and V
     are each split into hi + lo bfloat16 pairs (``split_bf16``) and the
     product is formed from the three leading terms
@@ -121,17 +129,19 @@ def kmatvec_bf16x3_emulated(X, V, kernel, l, f, s, block=512, workers=1):
 
     Like ``kmatvec_bf16_emulated`` this predicts a kernel's arithmetic; it is
     pinned by the split's error bound against the FP64 product, not by a value
-    the paper prints.
+    the paper prints.  ``rows`` (a slice, default all) restricts the output to
+    those rows.
     """
     X = np.asarray(X, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
-    n = X.shape[0]
+    sel, off = _out_rows(X.shape[0], rows)
     Vh, Vl = split_bf16(V)
-    Y = np.empty_like(V)
+    Y = np.empty((sel.stop - sel.start,) + V.shape[1:])
 
-    def one(rows):
-        Kh, Kl = split_bf16(kernel_value(sqdist(X[rows], X), kernel, l))
-        Y[rows] = (f * f) * (Kh @ Vh + Kh @ Vl + Kl @ Vh) + s * V[rows]
+    def one(b):
+        r = slice(b.start + off, b.stop + off)
+        Kh, Kl = split_bf16(kernel_value(sqdist(X[r], X), kernel, l))
+        Y[b] = (f * f) * (Kh @ Vh + Kh @ Vl + Kl @ Vh) + s * V[r]
 
-    _run_blocks(one, n, block, workers)
+    _run_blocks(one, sel.stop - sel.start, block, workers)
     return Y

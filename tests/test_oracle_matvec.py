@@ -140,3 +140,14 @@ def test_bf16x3_emulated_within_split_bound(kern):
     Z = W.rademacher(80, 3, 11)
     gz = oracle.kmatvec_bf16x3_emulated(X, Z, kern, l, f, 0.0, block=32)
     assert np.all(np.abs(gz - f * f * (K @ Z)) <= 1.01 * 2.0 ** -16 * f * f * (np.abs(K) @ np.abs(Z)) + 1e-14)
+
+
+def test_bf16_emulated_row_subsets_equal_full_rows():
+    """``rows`` only restricts the output: each subset equals the same rows of
+    the full result bit for bit, across block boundaries and at the end."""
+    X, V = _prob(300, 3, 5, 21)
+    for fn in (oracle.kmatvec_bf16_emulated, oracle.kmatvec_bf16x3_emulated):
+        full = fn(X, V, oracle.GAUSSIAN, 0.3, 1.1, 0.01, block=64)
+        for rows in (slice(0, 37), slice(100, 190), slice(250, 300), slice(299, None)):
+            part = fn(X, V, oracle.GAUSSIAN, 0.3, 1.1, 0.01, block=16, rows=rows)
+            np.testing.assert_array_equal(part, full[rows])
