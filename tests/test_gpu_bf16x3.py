@@ -20,7 +20,7 @@ import torch
 import oracle
 import paper_2503_02259_amd as hg
 from paper_2503_02259_amd import workloads as W
-from helpers import as_prec, colrel, colrel_cond, to_dev
+from helpers import as_prec, colrel, colrel_cond, oracle_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -161,3 +161,28 @@ def test_single_bf16_pcg_on_mixture_reports_failure(mixture_sub):
     assert not info["converged"].any()
     assert np.all(info["iters"] <= 300)
     assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+def test_full_size_precision_forms_sampled_rows():
+    # The precision-form workload at full size (n = 500,000 in d = 8, k = 33),
+    # in the calls the benchmark times: rows at the start, the middle and the
+    # ragged end (500,000 is not a multiple of the 128-point tile) against the
+    # oracle restricted to those rows.  Same bars as the subsample tests.
+    prob = W.workload_bf16_mixture()
+    X = as_prec(prob.X, torch.float32)
+    V = as_prec(prob.extra["V"], torch.float32)
+    Xd, Vd = to_dev(X, torch.float32), to_dev(V, torch.float32)
+    n = X.shape[0]
+    Y = {prec: hg.kmatvec(Xd, Vd, 0, prob.l, prob.f, prob.s, precision=prec).cpu().numpy()
+         for prec in ("bf16", "bf16x3", "fp32")}
+    del Xd, Vd
+    for rows in (slice(0, 64), slice(n // 2 - 32, n // 2 + 32), slice(n - 64, n)):
+        kw = dict(block=16, workers=8, rows=rows)
+        e1 = colrel(Y["bf16"][rows], oracle.kmatvec_bf16_emulated(X, V, 0, prob.l, prob.f, prob.s,
+                                                                   **kw)).max()
+        e3 = colrel(Y["bf16x3"][rows], oracle.kmatvec_bf16x3_emulated(X, V, 0, prob.l, prob.f,
+                                                                       prob.s, **kw)).max()
+        ef = colrel(Y["fp32"][rows], oracle_rows(X, V, 0, prob.l, prob.f, prob.s, rows)).max()
+        print("rows %s: bf16 vs emulated %.2e, split vs emulated %.2e, fp32 vs FP64 %.2e"
+              % (rows, e1, e3, ef))
+        assert e1 <= 1e-3 and e3 <= 1e-4 and ef <= 1e-5

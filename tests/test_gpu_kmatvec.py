@@ -85,6 +85,21 @@ def test_full_size_fp32_sampled_rows(kernel):
     assert np.all(np.abs(lhs - rhs) <= 1e-5 * np.abs(K1).sum() * np.abs(V).max(0))
 
 
+@pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
+def test_full_size_fp64_sampled_rows(kernel):
+    # The FP64 MatVec at n = 100,000, d = 3, k = 33 (the residual replacement
+    # of the refined solves at that size): rows at both ends and in the middle
+    # against the oracle, to the FP64 bar.
+    prob = W.workload_fp32_matvec(kernel=kernel)
+    X, V = prob.X, prob.extra["V"]
+    Y = hg.kmatvec(to_dev(X, torch.float64), to_dev(V, torch.float64), kernel, prob.l, prob.f,
+                   prob.s).cpu().numpy()
+    n = X.shape[0]
+    for rows in (slice(0, 64), slice(n // 2 - 40, n // 2 + 40), slice(n - 100, n)):
+        ref = oracle_rows(X, V, kernel, prob.l, prob.f, prob.s, rows)
+        assert colrel(Y[rows], ref).max() <= 1e-10
+
+
 HIGH_D = [(700, 9, 33), (513, 12, 5), (1001, 16, 64), (300, 17, 1), (1500, 20, 33),
           (257, 25, 17), (900, 32, 2)]
 
