@@ -99,6 +99,10 @@ def main():
                          "lowest p50 at full throughput in a sweep over 4-64)")
     ap.add_argument("--serve-rank", type=int, default=512,
                     help="Nyström rank of the second serving replay (0: skip it)")
+    ap.add_argument("--serve-rates", default="", metavar="R1,R2,...",
+                    help="also replay the same requests at these arrival rates (per second; "
+                         "the stream's own rate is 200/s), Jacobi and Nyström: latency at "
+                         "lower offered load, for context")
     ap.add_argument("--mixture-form", choices=("fp32", "bf16", "bf16x3"), default=None,
                     help="time only this form's MatVec on the n=500,000 d=8 mixture "
                          "(for profiling) and print its own JSON line")
@@ -272,6 +276,16 @@ def main():
         if args.serve_rank > 0:
             out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank,
                                                slots=args.serve_slots)
+    if "serve" in legs and args.serve > 0 and args.serve_rates:
+        sweep = []
+        for rate in (float(x) for x in args.serve_rates.split(",")):
+            for rank in (0, args.serve_rank):
+                res = leg_serve(args.serve, precond_rank=rank, slots=args.serve_slots,
+                                rate=rate)
+                sweep.append(dict(rate_per_s=rate, precond="nystrom%d" % rank if rank else "jacobi",
+                                  **{k: res[k] for k in ("p50_s", "p99_s", "solves_per_s",
+                                                         "span_s", "converged")}))
+        out["serving_rate_sweep"] = sweep
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, rows=args.cpu_rows or None)
     print(json.dumps(out))
@@ -543,12 +557,13 @@ def leg_paper_shape(kernel):
                               "inference 1.76 s")
 
 
-def leg_serve(nreq, precond_rank=0, slots=8):
+def leg_serve(nreq, precond_rank=0, slots=8, rate=200.0):
     """Continuous batching: the first `nreq` requests of the Poisson stream
     (rate 200/s; n log-uniform in [1e3, 2e5]; d ∈ {2,3,8}; l ~ U[0.05,0.5];
     s = 1e-2; FP32), each CG to 1e-6 (Jacobi, or the Nyström preconditioner
     of rank `precond_rank`) + SLQ 16 probes × 40 steps; at most `slots`
-    requests active at once."""
+    requests active at once.  Another `rate` replays the same requests with
+    their arrival times scaled by 200/rate."""
     import torch
     from paper_2503_02259_amd import workloads as W
     from paper_2503_02259_amd.serve import Server, replay
@@ -567,11 +582,11 @@ def leg_serve(nreq, precond_rank=0, slots=8):
 
     srv = Server(hbm_budget=128 << 30, max_active=slots)
     r = replay(reqs, srv, upload, tol=1e-6, max_iter=1000, nsteps=40, on_done=done,
-               precond_rank=precond_rank)
+               precond_rank=precond_rank, time_scale=200.0 / rate)
     srv.close()
     pc = "Nystrom rank %d" % precond_rank if precond_rank else "Jacobi"
-    return dict(workload="%d of 512 Poisson requests (200/s), CG 1e-6 (%s) + SLQ 16x40, FP32, "
-                         "%d slots" % (nreq, pc, slots), slots=slots,
+    return dict(workload="%d of 512 Poisson requests (%g/s), CG 1e-6 (%s) + SLQ 16x40, FP32, "
+                         "%d slots" % (nreq, rate, pc, slots), slots=slots,
                 requests=nreq, p50_s=r["p50"], p99_s=r["p99"], solves_per_s=r["throughput"],
                 span_s=r["span"], cg_iters_mean=float(np.mean([x[0] for x in stats])),
                 converged=int(sum(x[1] for x in stats)))
