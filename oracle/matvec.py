@@ -32,20 +32,28 @@ def _run_blocks(fn, n, block, workers):
             list(ex.map(fn, blocks))
 
 
-def kmatvec(X, V, kernel, l, f, s, block=512, workers=1):
-    """Y = K̂·V with K̂ = f²·k(X, X; l) + s·I.  X is n×d, V is n×k (or n)."""
+def _out_rows(n, rows):
+    """The output rows (a slice of range(n)) and their offset in the result."""
+    sel = slice(0, n) if rows is None else slice(*rows.indices(n)[:2])
+    return sel, sel.start
+
+
+def kmatvec(X, V, kernel, l, f, s, block=512, workers=1, rows=None):
+    """Y = K̂·V with K̂ = f²·k(X, X; l) + s·I.  X is n×d, V is n×k (or n).
+    ``rows`` (a slice, default all) restricts the output to those rows."""
     X = np.asarray(X, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     vec = V.ndim == 1
     V2 = V[:, None] if vec else V
-    n = X.shape[0]
-    Y = np.empty_like(V2)
+    sel, off = _out_rows(X.shape[0], rows)
+    Y = np.empty((sel.stop - sel.start, V2.shape[1]))
 
-    def one(rows):
-        K = kernel_value(sqdist(X[rows], X), kernel, l)
-        Y[rows] = (f * f) * (K @ V2) + s * V2[rows]
+    def one(b):
+        r = slice(b.start + off, b.stop + off)
+        K = kernel_value(sqdist(X[r], X), kernel, l)
+        Y[b] = (f * f) * (K @ V2) + s * V2[r]
 
-    _run_blocks(one, n, block, workers)
+    _run_blocks(one, sel.stop - sel.start, block, workers)
     return Y[:, 0] if vec else Y
 
 
@@ -79,12 +87,6 @@ def round_bf16(a):
     a = np.asarray(a, dtype=np.float64)
     m, e = np.frexp(a)               # a = m·2^e, 0.5 ≤ |m| < 1
     return np.ldexp(np.round(m * 256.0), e - 8)   # np.round: half to even
-
-
-def _out_rows(n, rows):
-    """The output rows (a slice of range(n)) and their offset in the result."""
-    sel = slice(0, n) if rows is None else slice(*rows.indices(n)[:2])
-    return sel, sel.start
 
 
 def kmatvec_bf16_emulated(X, V, kernel, l, f, s, block=512, workers=1, rows=None):

@@ -142,12 +142,14 @@ def test_bf16x3_emulated_within_split_bound(kern):
     assert np.all(np.abs(gz - f * f * (K @ Z)) <= 1.01 * 2.0 ** -16 * f * f * (np.abs(K) @ np.abs(Z)) + 1e-14)
 
 
-def test_bf16_emulated_row_subsets_equal_full_rows():
+def test_row_subsets_equal_full_rows():
     """``rows`` only restricts the output: each subset equals the same rows of
-    the full result bit for bit, across block boundaries and at the end."""
+    the full result, across block boundaries and at the end, up to the
+    rounding of the row-block products (BLAS may round a row differently with
+    another number of rows in its block)."""
     X, V = _prob(300, 3, 5, 21)
-    for fn in (oracle.kmatvec_bf16_emulated, oracle.kmatvec_bf16x3_emulated):
+    for fn in (oracle.kmatvec, oracle.kmatvec_bf16_emulated, oracle.kmatvec_bf16x3_emulated):
         full = fn(X, V, oracle.GAUSSIAN, 0.3, 1.1, 0.01, block=64)
         for rows in (slice(0, 37), slice(100, 190), slice(250, 300), slice(299, None)):
             part = fn(X, V, oracle.GAUSSIAN, 0.3, 1.1, 0.01, block=16, rows=rows)
-            np.testing.assert_array_equal(part, full[rows])
+            np.testing.assert_allclose(part, full[rows], rtol=1e-13, atol=1e-13 * np.abs(full).max())
