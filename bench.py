@@ -50,29 +50,36 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(prob, rows=None, workers=None):
-    """Time the oracle MatVec on the first `rows` rows (all n columns)."""
+    """Time the oracle MatVec (``oracle.kmatvec``, 128-row blocks on a thread
+    pool, one BLAS thread per block) on the first `rows` rows (all n
+    columns)."""
     import oracle
     from threadpoolctl import threadpool_limits
     X, V = prob.X.astype(np.float32).astype(np.float64), prob.extra["V"].astype(np.float32).astype(np.float64)
-    rows = min(rows or X.shape[0], X.shape[0])
-    workers = workers or min(16, os.cpu_count() or 1)
-    Xs = X  # all n points as columns; only `rows` rows of K̂ are formed
     n = X.shape[0]
+    rows = min(rows or n, n)
+    workers = workers or min(16, os.cpu_count() or 1)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        from concurrent.futures import ThreadPoolExecutor
-        blocks = [slice(i, min(i + 128, rows)) for i in range(0, rows, 128)]
-
-        def one(b):
-            K = oracle.kernel_value(oracle.sqdist(Xs[b], Xs), prob.kernel, prob.l)
-            return prob.f ** 2 * (K @ V) + prob.s * V[b]
-
-        with ThreadPoolExecutor(max_workers=workers) as ex:
-            list(ex.map(one, blocks))
+        oracle.kmatvec(X, V, prob.kernel, prob.l, prob.f, prob.s, block=128, workers=workers,
+                       rows=slice(0, rows))
         dt = time.perf_counter() - t0
     k = V.shape[1]
     return dict(value=rows * n * k / dt, unit="kernel-evals*vectors/s", cores=workers, kind="oracle",
+                cpu_model=cpu_model(),
                 sample="FP64 oracle MatVec on rows 0..%d of the n=%d, k=%d workload "
                        "(%d×%d kernel values), %.1f s" % (rows - 1, n, k, rows, n, dt))
 
