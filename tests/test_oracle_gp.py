@@ -137,3 +137,25 @@ def test_hutchpp_unbiased_and_lower_variance_for_decaying_spectrum():
         assert np.all(np.abs(hp.mean(axis=0) - e) <= 3.5 * se), (hp.mean(0), e, se)
         if l == 1.0:
             assert hp[:, 0].std() < 0.6 * hu[:, 0].std()
+
+
+def test_orth_range_rank_and_projection():
+    """orth_range returns orthonormal columns spanning exactly range(Y): for
+    Y = A·B with A n×3 and B 3×5 (rank 3, with a duplicated and a zero
+    column), Q has 3 columns, QᵀQ = I, and the projector QQᵀ reproduces Y;
+    a zero matrix has an empty range."""
+    g = np.random.default_rng(5)
+    A = g.standard_normal((40, 3))
+    B = g.standard_normal((3, 5))
+    Y = A @ B
+    Y[:, 3] = Y[:, 0]
+    Y[:, 4] = 0.0
+    Q = oracle.orth_range(Y)
+    assert Q.shape == (40, 3)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(3), atol=1e-12)
+    np.testing.assert_allclose(Q @ (Q.T @ Y), Y, atol=1e-12 * np.abs(Y).max())
+    # a vector outside range(A) is not reproduced
+    w = g.standard_normal(40)
+    w -= A @ np.linalg.lstsq(A, w, rcond=None)[0]
+    assert np.linalg.norm(Q @ (Q.T @ w)) <= 1e-12 * np.linalg.norm(w)
+    assert oracle.orth_range(np.zeros((10, 4))).shape == (10, 0)
