@@ -69,8 +69,9 @@ typedef enum {
 
 /* Problem flags.
  * HIGP_FLAG_NO_SYMMETRIC: the FP32 square MatVec with k ≤ 2 vectors and
- *   d ≤ 4 at 32768 ≤ n (up to about 4·10⁵ for k = 2, 5.6·10⁵ for k = 1,
- *   where its per-block-pair slots reach 2 GiB) normally evaluates each
+ *   d ≤ 4 (or k = 1 and d ≤ 8) at 32768 ≤ n (up to about 4·10⁵ for k = 2,
+ *   5.6·10⁵ for k = 1, where its per-block-pair slots reach 2 GiB)
+ *   normally evaluates each
  *   kernel value of a pair of
  *   point blocks once and uses it for both output blocks (K̂ is symmetric:
  *   about n²/2 kernel values instead of n²).  This flag selects the

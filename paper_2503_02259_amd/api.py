@@ -60,7 +60,7 @@ def _stream(stream, device):
 def problem(X, kernel, l, f, s, precision=None, symmetric=True):
     """The ABI problem struct for points X (n×d device tensor).
     symmetric=False selects the full-block FP32 MatVec where the symmetric
-    one would apply (k ≤ 2, d ≤ 4, n ≥ 32768)."""
+    one would apply (n ≥ 32768 and k ≤ 2 with d ≤ 4, or k = 1 with d ≤ 8)."""
     if X.dim() != 2:
         raise ValueError("X must be n×d")
     p = _lib.Problem()

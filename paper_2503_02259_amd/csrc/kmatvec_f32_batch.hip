@@ -125,7 +125,7 @@ struct SymJob {
 
 template <int KERN, bool DIAG>
 __device__ __forceinline__ void sym_unit(const SymArgs& a, int dcode, int A, int B, int64_t item,
-                                         SymLds<1>& L) {
+                                         SymLds<1, 1>& L) {
   if (dcode == 2) sym_pair<KERN, 2, 1, DIAG>(a, A, B, item, L);
   else if (dcode == 3) sym_pair<KERN, 3, 1, DIAG>(a, A, B, item, L);
   else sym_pair<KERN, 4, 1, DIAG>(a, A, B, item, L);
@@ -134,7 +134,7 @@ __device__ __forceinline__ void sym_unit(const SymArgs& a, int dcode, int A, int
 __global__ __launch_bounds__(256) void kmv_f32_batch_sym(const SymJob* __restrict__ jobs,
                                                          int njobs, int64_t total,
                                                          unsigned long long* counter) {
-  __shared__ SymLds<1> L;
+  __shared__ SymLds<1, 1> L;
   __shared__ long long unit_sh;
   for (;;) {
     if (threadIdx.x == 0) unit_sh = (long long)atomicAdd(counter, 1ull);
@@ -331,7 +331,7 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
     const BatchMatvec& J = jobs[i];
     if (J.k < 1 || J.k > 32)
       return set_error(HIGP_ERR_UNSUPPORTED, "batched MatVec supports 1 <= k <= 32");
-    if (J.k == 1 && sym_eligible(J.n, J.d, 1, J.flags)) {
+    if (J.k == 1 && sym_eligible(J.n, J.d, 1, J.flags, 4)) {
       sym.push_back(&J);
       continue;
     }

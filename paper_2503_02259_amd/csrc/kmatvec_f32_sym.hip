@@ -30,7 +30,7 @@ namespace {
 
 template <int KERN, int D, int K>
 __global__ __launch_bounds__(256) void kmv_f32_sym(SymArgs a) {
-  __shared__ SymLds<K> L;
+  __shared__ SymLds<K, sym_nq<D>()> L;
   int A, B;
   item_pair(blockIdx.x, a.ns, A, B);
   if (A == B)
@@ -51,7 +51,9 @@ SymFn pick_sym(int d, int k) {
   switch (dim_code(d)) {
     case 2: return pick_sym_k<KERN, 2>(k);
     case 3: return pick_sym_k<KERN, 3>(k);
-    default: return pick_sym_k<KERN, 4>(k);
+    case 4: return pick_sym_k<KERN, 4>(k);
+    case 8: return pick_sym_k<KERN, 8>(k);
+    default: return nullptr;  // d > 8: not eligible
   }
 }
 
@@ -60,14 +62,20 @@ SymFn pick_sym(int d, int k) {
 // The slots of the block pairs grow as n²/1024 (2·4·k bytes per pair and
 // point of a block); above 2 GiB of slots the full-block form is used.
 bool kmatvec_f32_sym_applies(const Problem& p, int k) {
-  return sym_eligible(p.n, p.d, k, p.flags);
+  // d = 5..8 stages two float4s per point and fits one workgroup per CU:
+  // 1.12× the full-block form for one vector (n = 1e5), no gain for two.
+  return sym_eligible(p.n, p.d, k, p.flags, k == 1 ? 8 : 4);
 }
 
 int launch_kmatvec_f32_sym(const Problem& p, int k, const void* Vin, void* Y, hipStream_t st) {
   const int ns = (int)((p.n + kSymSuper - 1) / kSymSuper);
   const int64_t items = (int64_t)ns * (ns + 1) / 2;
   if (items > 0x7fffffffLL) return set_error(HIGP_ERR_INVALID_ARG, "n too large");
-  const size_t xp_bytes = ((size_t)p.n * 4 * 4 + 255) / 256 * 256;
+  const SymFn fn = p.kernel == HIGP_GAUSSIAN ? pick_sym<HIGP_GAUSSIAN>(p.d, k)
+                                             : pick_sym<HIGP_MATERN32>(p.d, k);
+  if (fn == nullptr) return set_error(HIGP_ERR_INVALID_ARG, "symmetric form needs d <= 8");
+  const int P = p.d <= 4 ? 4 : 8;  // floats per prepared point
+  const size_t xp_bytes = ((size_t)p.n * P * 4 + 255) / 256 * 256;
   const size_t slot_bytes = (size_t)items * kSymSuper * k * 4;
   void* scratch = nullptr;
   HIGP_TRY(scratch_alloc(&scratch, xp_bytes + 2 * slot_bytes, st));
@@ -80,11 +88,9 @@ int launch_kmatvec_f32_sym(const Problem& p, int k, const void* Vin, void* Y, hi
   a.n = p.n;
   a.ns = ns;
   const float xs = (float)coord_scale(p.kernel, HIGP_FP32, p.l);
-  hipLaunchKernelGGL(prep_points_f32, dim3((unsigned)std::min<int64_t>((p.n * 4 + 255) / 256, 4096)),
-                     dim3(256), 0, st, p.n, p.n, p.d, 4, static_cast<const float*>(p.X), xs,
+  hipLaunchKernelGGL(prep_points_f32, dim3((unsigned)std::min<int64_t>((p.n * P + 255) / 256, 4096)),
+                     dim3(256), 0, st, p.n, p.n, p.d, P, static_cast<const float*>(p.X), xs,
                      const_cast<float*>(a.Xp));
-  const SymFn fn = p.kernel == HIGP_GAUSSIAN ? pick_sym<HIGP_GAUSSIAN>(p.d, k)
-                                             : pick_sym<HIGP_MATERN32>(p.d, k);
   hipLaunchKernelGGL(fn, dim3((unsigned)items), dim3(256), 0, st, a);
   const unsigned fb = (unsigned)std::min<int64_t>((p.n * k + 255) / 256, 4096);
   if (k == 1)

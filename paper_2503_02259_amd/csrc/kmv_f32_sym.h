@@ -16,7 +16,7 @@ constexpr int kSymSuper = kSymTile * kSymSub;  // points per super block
 constexpr int kMicro = 8;                      // micro tile edge
 
 struct SymArgs {
-  const float* Xp;  // prepared points, 4 floats each; rows ≥ n are read as far sentinels
+  const float* Xp;  // prepared points, 4·NQ floats each; rows ≥ n are read as far sentinels
   const float* V;   // n×k; rows ≥ n are read as 0
   float* prow;      // [item][1024][k] row sums (Y_A part)
   float* pcol;      // [item][1024][k] column sums (Y_B part, A < B)
@@ -25,10 +25,13 @@ struct SymArgs {
 };
 
 // Whether a square FP32 MatVec of n points in d dimensions with k vectors
-// takes the symmetric form: one or two vectors, d ≤ 4, enough block pairs to
-// fill the chip, and per-pair slots of at most 2 GiB (they grow as n²/1024).
-inline bool sym_eligible(int64_t n, int d, int k, int flags) {
-  if (k > 2 || d > 4 || n < kSymMinPoints || (flags & HIGP_FLAG_NO_SYMMETRIC) != 0) return false;
+// takes the symmetric form: one or two vectors, d ≤ max_d (a single MatVec:
+// 8 for one vector, 4 for two; the batched launch stages one float4 per
+// point, so 4), enough block pairs to fill the chip, and per-pair slots of at
+// most 2 GiB (they grow as n²/1024).
+inline bool sym_eligible(int64_t n, int d, int k, int flags, int max_d) {
+  if (k > 2 || d > max_d || n < kSymMinPoints || (flags & HIGP_FLAG_NO_SYMMETRIC) != 0)
+    return false;
   const int64_t ns = (n + kSymSuper - 1) / kSymSuper;
   const int64_t slot_bytes = ns * (ns + 1) / 2 * kSymSuper * k * 4;
   return 2 * slot_bytes <= (int64_t(1) << 31);
@@ -49,6 +52,12 @@ __host__ __device__ __forceinline__ int64_t item_index(int A, int B, int ns) {
   return (int64_t)A * ns - (int64_t)A * (A - 1) / 2 + (B - A);
 }
 
+// float4s per staged point: one for d ≤ 4, two for d ≤ 8.
+template <int D>
+constexpr int sym_nq() {
+  return D > 4 ? 2 : 1;
+}
+
 // Both super blocks (points and vectors) are staged in LDS once per pair.
 // Thread (tr, tc) of the 16×16 grid takes rows ii·16 + tr and columns
 // jj·16 + tc (ii, jj < 8) of each 128×128 tile, so that the 16-byte point
@@ -61,19 +70,19 @@ constexpr int part_bufs() {
   return K == 1 ? 2 : 1;
 }
 
-template <int K>
+template <int K, int NQ>
 struct SymLds {
-  float4 x[2][kSymSuper];                       // [0]: rows (A), [1]: columns (B)
+  float4 x[2][kSymSuper * NQ];                  // [0]: rows (A), [1]: columns (B)
   float v[2][kSymSuper * K];
   float part[part_bufs<K>()][16][kSymTile * K];  // per-group partial sums
   float colacc[kSymSuper * K];                  // column sums of the pair (B side)
 };
 
-template <int K>
+template <int K, int NQ>
 __device__ __forceinline__ void stage_block(const SymArgs& a, int64_t p0, float4* x, float* v) {
-  for (int e = threadIdx.x; e < kSymSuper; e += 256)
-    x[e] = p0 + e < a.n ? *reinterpret_cast<const float4*>(a.Xp + (p0 + e) * 4)
-                        : make_float4(kFar, kFar, kFar, kFar);
+  for (int e = threadIdx.x; e < kSymSuper * NQ; e += 256)
+    x[e] = p0 + e / NQ < a.n ? *reinterpret_cast<const float4*>(a.Xp + (p0 * NQ + e) * 4)
+                             : make_float4(kFar, kFar, kFar, kFar);
   for (int e = threadIdx.x; e < kSymSuper * K; e += 256)
     v[e] = p0 * K + e < a.n * K ? a.V[p0 * K + e] : 0.0f;
 }
@@ -81,12 +90,13 @@ __device__ __forceinline__ void stage_block(const SymArgs& a, int64_t p0, float4
 // One block pair (A, B) with slots `item`; called by all 256 threads.
 template <int KERN, int D, int K, bool DIAG>
 __device__ __forceinline__ void sym_pair(const SymArgs& a, int A, int B, int64_t item,
-                                         SymLds<K>& L) {
+                                         SymLds<K, sym_nq<D>()>& L) {
+  constexpr int NQ = sym_nq<D>();
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   const int rs = DIAG ? 1 : 0;  // row side: the column block itself on the diagonal
   for (int e = tid; e < kSymSuper * K; e += 256) L.colacc[e] = 0.0f;
-  if (!DIAG) stage_block<K>(a, (int64_t)A * kSymSuper, L.x[0], L.v[0]);
-  stage_block<K>(a, (int64_t)B * kSymSuper, L.x[1], L.v[1]);
+  if (!DIAG) stage_block<K, NQ>(a, (int64_t)A * kSymSuper, L.x[0], L.v[0]);
+  stage_block<K, NQ>(a, (int64_t)B * kSymSuper, L.x[1], L.v[1]);
   __syncthreads();
   float* prow = a.prow + (size_t)item * kSymSuper * K;
   float* pcol = a.pcol + (size_t)item * kSymSuper * K;
@@ -96,11 +106,14 @@ __device__ __forceinline__ void sym_pair(const SymArgs& a, int A, int B, int64_t
 #pragma unroll
     for (int ii = 0; ii < kMicro; ++ii) {
       const int r = rt * kSymTile + ii * 16 + tr;
-      const float4 q = L.x[rs][r];
-      xi[ii][0] = q.x;
-      if (D > 1) xi[ii][1] = q.y;
-      if (D > 2) xi[ii][2] = q.z;
-      if (D > 3) xi[ii][3] = q.w;
+#pragma unroll
+      for (int h = 0; h < NQ; ++h) {
+        const float4 q = L.x[rs][r * NQ + h];
+        if (4 * h < D) xi[ii][4 * h] = q.x;
+        if (4 * h + 1 < D) xi[ii][4 * h + 1] = q.y;
+        if (4 * h + 2 < D) xi[ii][4 * h + 2] = q.z;
+        if (4 * h + 3 < D) xi[ii][4 * h + 3] = q.w;
+      }
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         vi[ii][c] = L.v[rs][r * K + c];
@@ -112,11 +125,14 @@ __device__ __forceinline__ void sym_pair(const SymArgs& a, int A, int B, int64_t
 #pragma unroll
       for (int jj = 0; jj < kMicro; ++jj) {
         const int q0 = ct * kSymTile + jj * 16 + tc;
-        const float4 q = L.x[1][q0];
-        xj[jj][0] = q.x;
-        if (D > 1) xj[jj][1] = q.y;
-        if (D > 2) xj[jj][2] = q.z;
-        if (D > 3) xj[jj][3] = q.w;
+#pragma unroll
+        for (int h = 0; h < NQ; ++h) {
+          const float4 q = L.x[1][q0 * NQ + h];
+          if (4 * h < D) xj[jj][4 * h] = q.x;
+          if (4 * h + 1 < D) xj[jj][4 * h + 1] = q.y;
+          if (4 * h + 2 < D) xj[jj][4 * h + 2] = q.z;
+          if (4 * h + 3 < D) xj[jj][4 * h + 3] = q.w;
+        }
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           vj[jj][c] = L.v[1][q0 * K + c];

@@ -140,13 +140,13 @@ def test_bf16_and_server_reject_high_dimension():
 
 
 SYM = [(40_000, 3, 1), (40_000, 3, 2), (33_001, 1, 1), (35_000, 2, 2), (32_768, 4, 1),
-       (50_000, 4, 2)]
+       (50_000, 4, 2), (40_000, 8, 1), (36_001, 5, 1), (33_000, 7, 1)]
 
 
 @pytest.mark.parametrize("kernel", [hg.GAUSSIAN, hg.MATERN32])
 @pytest.mark.parametrize("n,d,k", SYM)
 def test_symmetric_fp32_matvec(n, d, k, kernel):
-    # k ≤ 2, d ≤ 4, n ≥ 32768: each kernel value of a block pair serves both
+    # k ≤ 2 (d ≤ 4) or k = 1 (d ≤ 8), n ≥ 32768: each kernel value of a block pair serves both
     # output blocks.  Rows checked against the oracle where super blocks
     # (1024 points) and tiles (128) meet, at both ends and in the ragged last
     # block; every row against the full-block form.
