@@ -17,8 +17,23 @@ __global__ __launch_bounds__(kRedThreads) void coldot_kernel(int64_t n, int k, i
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   double s = 0.0;
-  if (c < k)
-    for (int64_t i = beg + r0; i < end; i += L.step) s += ld(A, i * k + c) * ld(B, i * k + c);
+  if (c < k) {
+    // Eight rows' loads in flight (two vectors, no stores: 28 µs at n = 1e5,
+    // k = 33, against 31 µs with four), products added in row order.
+    constexpr int RB = 2 * kRowBatch;
+    int64_t i = beg + r0;
+    for (; i + (RB - 1) * L.step < end; i += RB * L.step) {
+      double a[RB], b[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        a[u] = ld(A, (i + u * L.step) * k + c);
+        b[u] = ld(B, (i + u * L.step) * k + c);
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) s += a[u] * b[u];
+    }
+    for (; i < end; i += L.step) s += ld(A, i * k + c) * ld(B, i * k + c);
+  }
   (void)block_colsum_finish(s, k, work, counter, sh, [&](int col, double tot) { out[col] = tot; });
 }
 

@@ -109,7 +109,29 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update(int64_t n, int k, int6
     // The column's iteration count is raised only by the last block, after
     // every block has passed this point.
     if (S.ahist && blockIdx.x == 0 && r0 == 0) S.ahist[(size_t)S.iters[c] * k + c] = alpha;
-    for (int64_t i = beg + r0; i < end; i += L.step) {
+    // kRowBatch rows' loads in flight; the same arithmetic, ‖r‖² added in
+    // row order.
+    int64_t i = beg + r0;
+    for (; i + (kRowBatch - 1) * L.step < end; i += kRowBatch * L.step) {
+      double xv[kRowBatch], pv[kRowBatch], rv[kRowBatch], qv[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int64_t o = (i + u * L.step) * k + c;
+        xv[u] = S.x[o];
+        pv[u] = (double)p[o];
+        rv[u] = S.r[o];
+        qv[u] = (double)q[o];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int64_t o = (i + u * L.step) * k + c;
+        S.x[o] = xv[u] + alpha * pv[u];
+        const double rn = rv[u] - alpha * qv[u];
+        S.r[o] = rn;
+        acc += rn * rn;
+      }
+    }
+    for (; i < end; i += L.step) {
       const int64_t o = i * k + c;
       S.x[o] += alpha * (double)p[o];
       const double rn = S.r[o] - alpha * (double)q[o];

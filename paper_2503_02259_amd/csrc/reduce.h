@@ -15,7 +15,12 @@
 namespace higp {
 
 constexpr int kRedThreads = 256;  // 4 row lanes × 64 columns
-constexpr int kRedMaxBlocks = 1024;
+// At most 256 blocks: the last block adds G partials per column and every
+// block takes a ticket, so the tail grows with G.  At n = 1e5, k = 33 the
+// PCG update took 150 µs with up to 1024 blocks and 74 µs with 256 (128:
+// 137 µs, too few loads in flight).
+constexpr int kRedMaxBlocks = 256;
+constexpr int kRowBatch = 4;       // rows whose loads a thread keeps in flight
 
 struct RedGrid {
   int blocks;
@@ -85,13 +90,26 @@ __device__ __forceinline__ bool block_colsum_finish(double v, int k, double* wor
   if (ticket != gridDim.x - 1) return false;
   __threadfence();
   // Row lane r of column c adds the partials of blocks r, r + step, … in
-  // order; the lanes are then combined by the fixed tree.
+  // order; the lanes are then combined by the fixed tree.  Eight partials are
+  // loaded at a time (independent L2 round trips in flight) and added in the
+  // same order.
   const ColLanes L = col_lanes(k);
   double s = 0.0;
-  if (L.c < k)
-    for (unsigned b = L.r0; b < gridDim.x; b += L.step)
-      s += __hip_atomic_load(&work[(int64_t)b * 64 + L.c], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+  if (L.c < k) {
+    auto part = [&](unsigned b) {
+      return __hip_atomic_load(&work[(int64_t)b * 64 + L.c], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    };
+    unsigned b = L.r0;
+    for (; b + 7 * L.step < gridDim.x; b += 8 * L.step) {
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = part(b + u * L.step);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += w[u];
+    }
+    for (; b < gridDim.x; b += L.step) s += part(b);
+  }
   block_colsum(s, k, sh);
   if (tid < k) fin(tid, sh[tid]);
   if (tid == 0) *counter = 0u;
