@@ -88,8 +88,9 @@ struct BatchMatvec {
 size_t prepared_points_bytes(int64_t n, int d);
 int prepare_points_f32(const Problem& p, float* Xp, hipStream_t st);
 int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st, int num_cus);
-// Symmetric-tiled FP32 square MatVec Y = K̂V (k ≤ 2, d ≤ 4, large n; see
-// kmatvec_f32_sym.hip) and the test of whether it applies to (p, k).
+// Symmetric-tiled FP32 square MatVec Y = K̂V (k ≤ 2 with d ≤ 4 or k = 1 with
+// d ≤ 8, large n; see kmatvec_f32_sym.hip) and the test of whether it applies
+// to (p, k).
 bool kmatvec_f32_sym_applies(const Problem& p, int k);
 int launch_kmatvec_f32_sym(const Problem& p, int k, const void* V, void* Y, hipStream_t st);
 int batch_splits(int64_t n);

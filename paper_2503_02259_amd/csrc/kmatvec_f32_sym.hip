@@ -14,7 +14,9 @@
 // the contracted index on lane/32; using a K tile for Kᵀ would need a
 // cross-lane transpose, so the wide path stays unsymmetric.)
 //
-// Work inside a pair: both blocks are staged in LDS; 256 threads form a
+// Work inside a pair: both blocks are staged in LDS (a point as one float4
+// for d ≤ 4, two for d ≤ 8; the latter is taken for one vector only, where it
+// measured 1.12–1.20× the full-block form); 256 threads form a
 // 16×16 grid of 8×8 micro tiles over each 128×128 tile; row sums stay in
 // registers across the 8 column tiles, column sums of each column tile are
 // added over the 16 row groups through LDS in a fixed order.  Each pair writes its row and column sums to slots
