@@ -277,8 +277,15 @@ __global__ __launch_bounds__(256) void nys_tri_gemm(int64_t n, int r, const T* _
 
 // Row splits of WᵀR: enough blocks for several per CU (at k ≥ 4 a split has
 // ⌈r/64⌉ blocks) while each split keeps at least 512 rows.
-int wtr_splits(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(128, n / 512));
+// Row chunks S of the LᵀR pass: enough that the grid (⌈r/256⌉ landmark
+// blocks × S) has about 1024 workgroups, each chunk at least 64 rows, and
+// the S·r·kmax FP64 partials at most 64 MB.
+int wtr_splits(int64_t n, int r, int kmax) {
+  const int64_t bx = (r + 255) / 256;
+  int64_t s = (1024 + bx - 1) / bx;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, (64LL << 20) / ((int64_t)r * kmax * 8)));
+  return (int)std::max<int64_t>(1, s);
 }
 
 // The apply's two passes for k ≤ 3 on the VALU (wider blocks take the MFMA
@@ -312,11 +319,20 @@ __global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T*
     }
     __syncthreads();
     const int rows = (int)std::min<int64_t>(kRI, end - i0);
-    for (int ii = 0; ii < rows; ++ii) {
-      const double w = a < r ? (double)W[(i0 + ii) * r + a] : 0.0;
+    // Eight rows of W loaded at a time (independent loads in flight), then
+    // added in row order.
+    for (int i8 = 0; i8 < rows; i8 += 8) {
+      double w[8];
 #pragma unroll
-      for (int q = 0; q < QM; ++q)
-        if (q < Q) acc[q] = fma(w, rs[ii][cg + CG * q], acc[q]);
+      for (int u = 0; u < 8; ++u)
+        w[u] = a < r && i8 + u < rows ? (double)W[(i0 + i8 + u) * r + a] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i8 + u >= rows) break;
+#pragma unroll
+        for (int q = 0; q < QM; ++q)
+          if (q < Q) acc[q] = fma(w[u], rs[i8 + u][cg + CG * q], acc[q]);
+      }
     }
     __syncthreads();
   }
@@ -326,13 +342,30 @@ __global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T*
       if (q < Q) part[((int64_t)s * r + a) * k + cg + CG * q] = acc[q];
   }
 }
-__global__ void nys_reduce_parts(int rk, int S, const double* __restrict__ part,
-                                 double* __restrict__ Tm) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rk; e += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += part[(int64_t)s * rk + e];
-    Tm[e] = acc;
+// Tm[e] = Σ_s part[s][e]: eight lanes per output, lane j adding the chunks
+// s ≡ j (mod 8) in order with eight loads in flight, then the lanes combined
+// by a fixed butterfly.  32 outputs per block of 256.
+__global__ __launch_bounds__(256) void nys_reduce_parts(int rk, int S,
+                                                        const double* __restrict__ part,
+                                                        double* __restrict__ Tm) {
+  const int j = threadIdx.x & 7;
+  const int e = blockIdx.x * 32 + (threadIdx.x >> 3);
+  double acc = 0.0;
+  if (e < rk) {
+    int s = j;
+    for (; s + 56 < S; s += 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(s + 8 * u) * rk + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; s < S; s += 8) acc += part[(int64_t)s * rk + e];
   }
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 4);
+  if (e < rk && j == 0) Tm[e] = acc;
 }
 
 __global__ void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
@@ -371,10 +404,21 @@ __global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
       const int aa = e / k, c = e % k;
       us[aa][c] = a0 + aa < r ? u[(a0 + aa) * k + c] : 0.0;
     }
-    for (int e = threadIdx.x; e < NR * AC; e += 256) {
+    // NR·AC = 4096 elements, 16 per thread: all loads issued before the
+    // LDS stores.
+    static_assert(NR * AC == 16 * 256, "W chunk is 16 elements per thread");
+    double wl[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int e = threadIdx.x + 256 * m;
       const int rr = e / AC, ac = e % AC;
       const int64_t ir = (int64_t)blockIdx.x * NR + rr;
-      ws[rr][ac] = (ir < n && a0 + ac < r) ? (double)W[ir * r + a0 + ac] : 0.0;
+      wl[m] = (ir < n && a0 + ac < r) ? (double)W[ir * r + a0 + ac] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      ws[e / AC][e % AC] = wl[m];
     }
     __syncthreads();
     for (int aa = 0; aa < AC; ++aa) {
@@ -637,7 +681,7 @@ int build_impl(const Problem& p, int r, int kmax, NysPrec* P, hipStream_t st) {
   const int64_t n = p.n;
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
   const int fps_blocks = (int)std::min<int64_t>(256, (n + kThreads - 1) / kThreads);
-  const int S = wtr_splits(n);
+  const int S = wtr_splits(n, r, kmax);
   const int64_t chunk = (n + S - 1) / S;
   // Persistent part: L, C⁻¹, sel.  Work part (apply): partials, T, u.
   const size_t l_bytes = rup((size_t)n * r * sizeof(T));
@@ -782,8 +826,8 @@ int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t 
                        P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
   }
   const int rk = P.r * k;
-  hipLaunchKernelGGL(nys_reduce_parts, dim3(grid_for(rk)), dim3(256), 0, st, rk, P.S,
-                     (const double*)P.part, P.Tm);
+  hipLaunchKernelGGL(nys_reduce_parts, dim3((unsigned)((rk + 31) / 32)), dim3(256), 0, st, rk,
+                     P.S, (const double*)P.part, P.Tm);
   hipLaunchKernelGGL(nys_cinv_t, dim3(grid_for(rk)), dim3(256), 0, st, P.r, k,
                      (const double*)P.Cinv, (const double*)P.Tm, P.u);
   if (k >= 4) {
@@ -825,7 +869,7 @@ int nys_apply(const NysPrec& P, int k, const double* R, double* Z, hipStream_t s
 
 size_t nys_bytes(int64_t n, int rank, int kmax, int prec) {
   const int r = (int)std::min<int64_t>(rank, n);
-  const int S = wtr_splits(n);
+  const int S = wtr_splits(n, r, kmax);
   auto rup = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t es = prec == HIGP_FP64 ? 8 : 4;
   return rup((size_t)n * r * es) + rup((size_t)r * r * 8) + rup((size_t)r * 4) +
