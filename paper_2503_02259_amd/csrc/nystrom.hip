@@ -368,14 +368,33 @@ __global__ __launch_bounds__(256) void nys_reduce_parts(int rk, int S,
   if (e < rk && j == 0) Tm[e] = acc;
 }
 
-__global__ void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
-                           const double* __restrict__ Tm, double* __restrict__ u) {
-  const int total = r * k;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int a = e / k, c = e % k;
-    double acc = 0.0;
-    for (int b = 0; b < r; ++b) acc = fma(Cinv[(int64_t)a * r + b], Tm[b * k + c], acc);
-    u[e] = acc;
+// u = C⁻¹·T (r×r times r×k): one wave per row a of C⁻¹.  Lane l takes the
+// entries b ≡ l (mod 64) of the row (coalesced), for 16 columns at a time,
+// and the 64 lane sums of a column are added by a fixed butterfly.
+__global__ __launch_bounds__(256) void nys_cinv_t(int r, int k, const double* __restrict__ Cinv,
+                                                  const double* __restrict__ Tm,
+                                                  double* __restrict__ u) {
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= r) return;  // whole waves: no barrier follows
+  const double* row = Cinv + (int64_t)a * r;
+  for (int c0 = 0; c0 < k; c0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0;
+    for (int b = lane; b < r; b += 64) {
+      const double cv = row[b];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc)
+        if (c0 + cc < k) acc[cc] = fma(cv, Tm[(int64_t)b * k + c0 + cc], acc[cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      double v = acc[cc];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+      if (lane == 0 && c0 + cc < k) u[(int64_t)a * k + c0 + cc] = v;
+    }
   }
 }
 
@@ -828,7 +847,7 @@ int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t 
   const int rk = P.r * k;
   hipLaunchKernelGGL(nys_reduce_parts, dim3((unsigned)((rk + 31) / 32)), dim3(256), 0, st, rk,
                      P.S, (const double*)P.part, P.Tm);
-  hipLaunchKernelGGL(nys_cinv_t, dim3(grid_for(rk)), dim3(256), 0, st, P.r, k,
+  hipLaunchKernelGGL(nys_cinv_t, dim3((unsigned)((P.r + 3) / 4)), dim3(256), 0, st, P.r, k,
                      (const double*)P.Cinv, (const double*)P.Tm, P.u);
   if (k >= 4) {
     if (nb == 1) launch_apply_z_mfma<T, 1>(P, k, R, Z, st);
