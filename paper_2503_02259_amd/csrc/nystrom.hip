@@ -288,60 +288,6 @@ int wtr_splits(int64_t n, int r, int kmax) {
   return (int)std::max<int64_t>(1, s);
 }
 
-// The apply's two passes for k ≤ 3 on the VALU (wider blocks take the MFMA
-// forms below).
-// part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c].  A block covers 256/CG
-// landmarks a and CG column groups; a thread adds the columns c ≡ cg (mod
-// CG), c < k, of its landmark (CG = k), so that no FMA is spent on absent
-// columns.  Rows of R are staged in LDS kRI at a time.
-constexpr int kRI = 32;
-template <typename T, int CG>
-__global__ __launch_bounds__(256) void nys_wtr(int64_t n, int r, int k, const T* __restrict__ W,
-                                               const double* __restrict__ R, int64_t chunk,
-                                               double* __restrict__ part) {
-  constexpr int NA = 256 / CG;  // landmarks per block
-  constexpr int QM = 64 / CG;   // most columns per thread
-  __shared__ double rs[kRI][64];
-  const int la = threadIdx.x % NA, cg = threadIdx.x / NA;
-  const int a = blockIdx.x * NA + la;
-  const int s = blockIdx.y;
-  const int64_t beg = (int64_t)s * chunk;
-  const int64_t end = beg + chunk < n ? beg + chunk : n;
-  const int Q = (k - cg + CG - 1) / CG;  // this thread's columns
-  double acc[QM];
-#pragma unroll
-  for (int q = 0; q < QM; ++q) acc[q] = 0.0;
-  for (int64_t i0 = beg; i0 < end; i0 += kRI) {
-    for (int e = threadIdx.x; e < kRI * k; e += 256) {
-      const int ii = e / k, c = e % k;
-      const int64_t i = i0 + ii;
-      rs[ii][c] = i < end ? R[i * k + c] : 0.0;
-    }
-    __syncthreads();
-    const int rows = (int)std::min<int64_t>(kRI, end - i0);
-    // Eight rows of W loaded at a time (independent loads in flight), then
-    // added in row order.
-    for (int i8 = 0; i8 < rows; i8 += 8) {
-      double w[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        w[u] = a < r && i8 + u < rows ? (double)W[(i0 + i8 + u) * r + a] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (i8 + u >= rows) break;
-#pragma unroll
-        for (int q = 0; q < QM; ++q)
-          if (q < Q) acc[q] = fma(w[u], rs[i8 + u][cg + CG * q], acc[q]);
-      }
-    }
-    __syncthreads();
-  }
-  if (a < r) {
-#pragma unroll
-    for (int q = 0; q < QM; ++q)
-      if (q < Q) part[((int64_t)s * r + a) * k + cg + CG * q] = acc[q];
-  }
-}
 // Tm[e] = Σ_s part[s][e]: eight lanes per output, lane j adding the chunks
 // s ≡ j (mod 8) in order with eight loads in flight, then the lanes combined
 // by a fixed butterfly.  32 outputs per block of 256.
@@ -398,68 +344,9 @@ __global__ __launch_bounds__(256) void nys_cinv_t(int r, int k, const double* __
   }
 }
 
-// Z = (R − W·u)/s for an n×k block.  A block covers 256/CG rows and CG
-// column groups (as in nys_wtr); the landmark dimension is walked in chunks
-// of 16·CG, with the W and u chunks staged in LDS.
-template <typename T, int CG>
-__global__ __launch_bounds__(256) void nys_apply_z(int64_t n, int r, int k,
-                                                   const T* __restrict__ W,
-                                                   const double* __restrict__ u,
-                                                   const double* __restrict__ R, double inv_s,
-                                                   double* __restrict__ Z) {
-  constexpr int NR = 256 / CG;  // rows per block
-  constexpr int AC = 16 * CG;   // landmarks per LDS chunk
-  constexpr int QM = 64 / CG;
-  __shared__ double us[AC][64];
-  __shared__ double ws[NR][AC + 1];
-  const int lr = threadIdx.x % NR, cg = threadIdx.x / NR;
-  const int64_t i = (int64_t)blockIdx.x * NR + lr;
-  const int Q = (k - cg + CG - 1) / CG;
-  double acc[QM];
-#pragma unroll
-  for (int q = 0; q < QM; ++q) acc[q] = 0.0;
-  for (int a0 = 0; a0 < r; a0 += AC) {
-    for (int e = threadIdx.x; e < AC * k; e += 256) {
-      const int aa = e / k, c = e % k;
-      us[aa][c] = a0 + aa < r ? u[(a0 + aa) * k + c] : 0.0;
-    }
-    // NR·AC = 4096 elements, 16 per thread: all loads issued before the
-    // LDS stores.
-    static_assert(NR * AC == 16 * 256, "W chunk is 16 elements per thread");
-    double wl[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      const int rr = e / AC, ac = e % AC;
-      const int64_t ir = (int64_t)blockIdx.x * NR + rr;
-      wl[m] = (ir < n && a0 + ac < r) ? (double)W[ir * r + a0 + ac] : 0.0;
-    }
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      ws[e / AC][e % AC] = wl[m];
-    }
-    __syncthreads();
-    for (int aa = 0; aa < AC; ++aa) {
-      const double w = ws[lr][aa];
-#pragma unroll
-      for (int q = 0; q < QM; ++q)
-        if (q < Q) acc[q] = fma(w, us[aa][cg + CG * q], acc[q]);
-    }
-    __syncthreads();
-  }
-  if (i < n) {
-#pragma unroll
-    for (int q = 0; q < QM; ++q)
-      if (q < Q) {
-        const int c = cg + CG * q;
-        Z[i * k + c] = (R[i * k + c] - acc[q]) * inv_s;
-      }
-  }
-}
-
-// The same two passes for k ≥ 4 on v_mfma_f64_16x16x4f64 (NB blocks of 16
-// columns; lane layout: A[m][kk] from lane kk·16 + m, B[kk][c] from lane
+// The apply's two passes on v_mfma_f64_16x16x4f64 (NB = ⌈k/16⌉ blocks of 16
+// columns; one column costs a whole block, but the passes are bound by
+// reading L and by latency, not by MFMA time; lane layout: A[m][kk] from lane kk·16 + m, B[kk][c] from lane
 // kk·16 + c, result register e of lane l is C[l/16 + 4e][l%16]).
 //
 // part[s][a][c] = Σ_{i in chunk s} W[i][a]·R[i][c]: A = Wᵀ (16 landmarks ×
@@ -829,40 +716,20 @@ void launch_apply_z_mfma(const NysPrec& P, int k, const double* R, double* Z, hi
 
 template <typename T>
 int apply_impl(const NysPrec& P, int k, const double* R, double* Z, hipStream_t st) {
-  // k ≥ 4: FP64 MFMA passes (NB = ⌈k/16⌉ blocks of 16 columns); k ≤ 3: the
-  // VALU passes, which spend no work on absent columns.
   const int nb = (k + 15) / 16;
-  if (k >= 4) {
-    if (nb == 1) launch_wtr_mfma<T, 1>(P, k, R, st);
-    else if (nb == 2) launch_wtr_mfma<T, 2>(P, k, R, st);
-    else if (nb == 3) launch_wtr_mfma<T, 3>(P, k, R, st);
-    else launch_wtr_mfma<T, 4>(P, k, R, st);
-  } else if (k >= 2) {
-    hipLaunchKernelGGL((nys_wtr<T, 2>), dim3((P.r + 127) / 128, P.S), dim3(256), 0, st, P.n,
-                       P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
-  } else {
-    hipLaunchKernelGGL((nys_wtr<T, 1>), dim3((P.r + 255) / 256, P.S), dim3(256), 0, st, P.n,
-                       P.r, k, static_cast<const T*>(P.W), R, P.chunk, P.part);
-  }
+  if (nb == 1) launch_wtr_mfma<T, 1>(P, k, R, st);
+  else if (nb == 2) launch_wtr_mfma<T, 2>(P, k, R, st);
+  else if (nb == 3) launch_wtr_mfma<T, 3>(P, k, R, st);
+  else launch_wtr_mfma<T, 4>(P, k, R, st);
   const int rk = P.r * k;
   hipLaunchKernelGGL(nys_reduce_parts, dim3((unsigned)((rk + 31) / 32)), dim3(256), 0, st, rk,
                      P.S, (const double*)P.part, P.Tm);
   hipLaunchKernelGGL(nys_cinv_t, dim3((unsigned)((P.r + 3) / 4)), dim3(256), 0, st, P.r, k,
                      (const double*)P.Cinv, (const double*)P.Tm, P.u);
-  if (k >= 4) {
-    if (nb == 1) launch_apply_z_mfma<T, 1>(P, k, R, Z, st);
-    else if (nb == 2) launch_apply_z_mfma<T, 2>(P, k, R, Z, st);
-    else if (nb == 3) launch_apply_z_mfma<T, 3>(P, k, R, Z, st);
-    else launch_apply_z_mfma<T, 4>(P, k, R, Z, st);
-  } else if (k >= 2) {
-    hipLaunchKernelGGL((nys_apply_z<T, 2>), dim3((unsigned)((P.n + 127) / 128)), dim3(256), 0,
-                       st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
-                       1.0 / P.s, Z);
-  } else {
-    hipLaunchKernelGGL((nys_apply_z<T, 1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0,
-                       st, P.n, P.r, k, static_cast<const T*>(P.W), (const double*)P.u, R,
-                       1.0 / P.s, Z);
-  }
+  if (nb == 1) launch_apply_z_mfma<T, 1>(P, k, R, Z, st);
+  else if (nb == 2) launch_apply_z_mfma<T, 2>(P, k, R, Z, st);
+  else if (nb == 3) launch_apply_z_mfma<T, 3>(P, k, R, Z, st);
+  else launch_apply_z_mfma<T, 4>(P, k, R, Z, st);
   return hipGetLastError() == hipSuccess ? HIGP_OK
                                          : set_error(HIGP_ERR_HIP, "preconditioner apply failed");
 }
