@@ -106,6 +106,8 @@ def main():
                          "lowest p50 at full throughput in a sweep over 4-64)")
     ap.add_argument("--serve-rank", type=int, default=512,
                     help="Nyström rank of the second serving replay (0: skip it)")
+    ap.add_argument("--serve-skip-jacobi", action="store_true",
+                    help="skip the Jacobi serving replay (e.g. to profile the Nyström one alone)")
     ap.add_argument("--serve-rates", default="", metavar="R1,R2,...",
                     help="also replay the same requests at these arrival rates (per second; "
                          "the stream's own rate is 200/s), Jacobi and Nyström: latency at "
@@ -279,7 +281,8 @@ def main():
         for kname, kid in (("gaussian", 0), ("matern32", 1)):
             out["paper_shape_e2e_" + kname] = leg_paper_shape(kid)
     if "serve" in legs and args.serve > 0:
-        out["serving"] = leg_serve(args.serve, slots=args.serve_slots)
+        if not args.serve_skip_jacobi:
+            out["serving"] = leg_serve(args.serve, slots=args.serve_slots)
         if args.serve_rank > 0:
             out["serving_nystrom"] = leg_serve(args.serve, precond_rank=args.serve_rank,
                                                slots=args.serve_slots)
