@@ -120,21 +120,28 @@ struct SymJob {
   SymArgs a;
   int64_t first_unit;  // units of earlier jobs of the same launch
   int kernel;
-  int dcode;           // 2, 3 or 4
+  int dcode;           // 2, 3 or 4 (one float4 per point), 8 (two)
 };
 
-template <int KERN, bool DIAG>
+// NQ = 1: problems with d ≤ 4; NQ = 2: d = 5..8 (a launch of their own,
+// since the staged points take twice the LDS).
+template <int KERN, bool DIAG, int NQ>
 __device__ __forceinline__ void sym_unit(const SymArgs& a, int dcode, int A, int B, int64_t item,
-                                         SymLds<1, 1>& L) {
-  if (dcode == 2) sym_pair<KERN, 2, 1, DIAG>(a, A, B, item, L);
-  else if (dcode == 3) sym_pair<KERN, 3, 1, DIAG>(a, A, B, item, L);
-  else sym_pair<KERN, 4, 1, DIAG>(a, A, B, item, L);
+                                         SymLds<1, NQ>& L) {
+  if constexpr (NQ == 2) {
+    sym_pair<KERN, 8, 1, DIAG>(a, A, B, item, L);
+  } else {
+    if (dcode == 2) sym_pair<KERN, 2, 1, DIAG>(a, A, B, item, L);
+    else if (dcode == 3) sym_pair<KERN, 3, 1, DIAG>(a, A, B, item, L);
+    else sym_pair<KERN, 4, 1, DIAG>(a, A, B, item, L);
+  }
 }
 
+template <int NQ>
 __global__ __launch_bounds__(256) void kmv_f32_batch_sym(const SymJob* __restrict__ jobs,
                                                          int njobs, int64_t total,
                                                          unsigned long long* counter) {
-  __shared__ SymLds<1, 1> L;
+  __shared__ SymLds<1, NQ> L;
   __shared__ long long unit_sh;
   for (;;) {
     if (threadIdx.x == 0) unit_sh = (long long)atomicAdd(counter, 1ull);
@@ -154,11 +161,11 @@ __global__ __launch_bounds__(256) void kmv_f32_batch_sym(const SymJob* __restric
     int A, B;
     item_pair((int)item, a.ns, A, B);
     if (jobs[lo].kernel == HIGP_GAUSSIAN) {
-      if (A == B) sym_unit<HIGP_GAUSSIAN, true>(a, dcode, A, B, item, L);
-      else sym_unit<HIGP_GAUSSIAN, false>(a, dcode, A, B, item, L);
+      if (A == B) sym_unit<HIGP_GAUSSIAN, true, NQ>(a, dcode, A, B, item, L);
+      else sym_unit<HIGP_GAUSSIAN, false, NQ>(a, dcode, A, B, item, L);
     } else {
-      if (A == B) sym_unit<HIGP_MATERN32, true>(a, dcode, A, B, item, L);
-      else sym_unit<HIGP_MATERN32, false>(a, dcode, A, B, item, L);
+      if (A == B) sym_unit<HIGP_MATERN32, true, NQ>(a, dcode, A, B, item, L);
+      else sym_unit<HIGP_MATERN32, false, NQ>(a, dcode, A, B, item, L);
     }
     __syncthreads();
   }
@@ -252,6 +259,7 @@ int launch_batch_kind(const std::vector<BatchJob>& hj, const std::vector<const B
   return rc;
 }
 
+template <int NQ>
 int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st, int num_cus) {
   const int count = (int)src.size();
   if (count == 0) return HIGP_OK;
@@ -270,7 +278,7 @@ int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st,
     b.a.ns = ns;
     b.first_unit = total;
     b.kernel = J.kernel;
-    b.dcode = J.d <= 2 ? 2 : (J.d == 3 ? 3 : 4);
+    b.dcode = J.d <= 2 ? 2 : (J.d == 3 ? 3 : (J.d == 4 ? 4 : 8));
     hj[i] = b;
     slot_off[i] = slots;
     total += items;
@@ -294,10 +302,10 @@ int launch_batch_sym(const std::vector<const BatchMatvec*>& src, hipStream_t st,
       hipMemsetAsync(counter, 0, 8, st) != hipSuccess)
     rc = set_error(HIGP_ERR_HIP, "batch setup failed");
   static std::atomic<int> cache{0};
-  const int bpc = resident_blocks(reinterpret_cast<const void*>(kmv_f32_batch_sym), 0, cache);
+  const int bpc = resident_blocks(reinterpret_cast<const void*>(kmv_f32_batch_sym<NQ>), 0, cache);
   if (rc == HIGP_OK) {
     const int64_t grid = std::min<int64_t>(total, (int64_t)num_cus * bpc);
-    hipLaunchKernelGGL(kmv_f32_batch_sym, dim3((unsigned)grid), dim3(256), 0, st,
+    hipLaunchKernelGGL(kmv_f32_batch_sym<NQ>, dim3((unsigned)grid), dim3(256), 0, st,
                        (const SymJob*)djobs, count, total, counter);
     for (int i = 0; i < count; ++i) {
       const BatchMatvec& J = *src[i];
@@ -322,7 +330,7 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
   constexpr int kKinds = 6;  // kind 3 (symmetric) is collected separately
   std::vector<BatchJob> hj[kKinds];
   std::vector<const BatchMatvec*> src[kKinds];
-  std::vector<const BatchMatvec*> sym;
+  std::vector<const BatchMatvec*> sym[2];  // d ≤ 4, d = 5..8
   int64_t total[kKinds] = {0, 0, 0, 0, 0, 0};
   size_t part_elems[kKinds] = {0, 0, 0, 0, 0, 0};
   const int64_t rows_of[kKinds] = {kind_rows<0>(), kind_rows<1>(), kind_rows<2>(), 0,
@@ -331,8 +339,8 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
     const BatchMatvec& J = jobs[i];
     if (J.k < 1 || J.k > 32)
       return set_error(HIGP_ERR_UNSUPPORTED, "batched MatVec supports 1 <= k <= 32");
-    if (J.k == 1 && sym_eligible(J.n, J.d, 1, J.flags, 4)) {
-      sym.push_back(&J);
+    if (J.k == 1 && sym_eligible(J.n, J.d, 1, J.flags, 8)) {
+      sym[J.d <= 4 ? 0 : 1].push_back(&J);
       continue;
     }
     const int kind = J.k == 1 ? 1 : J.k == 2 ? 2 : J.k <= 16 ? 4 : J.k == 17 ? 5 : 0;
@@ -363,7 +371,8 @@ int launch_kmatvec_f32_batch(const BatchMatvec* jobs, int count, hipStream_t st,
   HIGP_TRY(launch_batch_kind<2>(hj[2], src[2], total[2], part_elems[2], st, num_cus));
   HIGP_TRY(launch_batch_kind<4>(hj[4], src[4], total[4], part_elems[4], st, num_cus));
   HIGP_TRY(launch_batch_kind<5>(hj[5], src[5], total[5], part_elems[5], st, num_cus));
-  HIGP_TRY(launch_batch_sym(sym, st, num_cus));
+  HIGP_TRY(launch_batch_sym<1>(sym[0], st, num_cus));
+  HIGP_TRY(launch_batch_sym<2>(sym[1], st, num_cus));
   return HIGP_OK;
 }
 

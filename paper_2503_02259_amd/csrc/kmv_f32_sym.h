@@ -25,10 +25,9 @@ struct SymArgs {
 };
 
 // Whether a square FP32 MatVec of n points in d dimensions with k vectors
-// takes the symmetric form: one or two vectors, d ≤ max_d (a single MatVec:
-// 8 for one vector, 4 for two; the batched launch stages one float4 per
-// point, so 4), enough block pairs to fill the chip, and per-pair slots of at
-// most 2 GiB (they grow as n²/1024).
+// takes the symmetric form: one or two vectors, d ≤ max_d (8 for one vector,
+// 4 for two; the batched launch serves one vector), enough block pairs to
+// fill the chip, and per-pair slots of at most 2 GiB (they grow as n²/1024).
 inline bool sym_eligible(int64_t n, int d, int k, int flags, int max_d) {
   if (k > 2 || d > max_d || n < kSymMinPoints || (flags & HIGP_FLAG_NO_SYMMETRIC) != 0)
     return false;

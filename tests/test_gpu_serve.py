@@ -121,20 +121,24 @@ def test_request_larger_than_budget_is_rejected():
     srv.close()
 
 
-def test_large_request_symmetric_matvec():
-    # n = 40,000 (d = 3): once its Lanczos columns are done, the request's
-    # single CG column takes the symmetric-tiled MatVec.  Its result is the
-    # same alone and in a mix, agrees with the full-block form to rounding,
-    # and its true residual (FP64 MatVec) is within twice the tolerance (the
-    # recursive residual drifts from the true one by the FP32 MatVec error).
+@pytest.mark.parametrize("d", [3, 8])
+def test_large_request_symmetric_matvec(d):
+    # n = 40,000 (d = 3, or 8 with two float4s per staged point): once its
+    # Lanczos columns are done, the request's single CG column takes the
+    # symmetric-tiled MatVec.  Its result is the same alone and in a mix
+    # (with a d = 3 and a d = 8 request beside it), agrees with the
+    # full-block form to rounding, and its true residual (FP64 MatVec) is
+    # within twice the tolerance (the recursive residual drifts from the true
+    # one by the FP32 MatVec error).
     import paper_2503_02259_amd as hg
     n = 40_000
-    big = _req(n, 3, 50, nprobe=4)
-    small = [_req(m, 3, 60 + i, nprobe=4) for i, m in enumerate([1500, 2500])]
+    l = 0.1 if d == 3 else 0.4  # kernel values well away from the identity in 8 dimensions
+    big = _req(n, d, 50, nprobe=4)
+    small = [_req(m, dm, 60 + i, nprobe=4) for i, (m, dm) in enumerate([(1500, 3), (2500, 8)])]
 
     def run(reqs, symmetric=True):
         srv = Server(hbm_budget=16 << 30, max_active=8)
-        ids = [srv.submit(*_upload(*r), l=0.1, s=0.1, tol=1e-5, max_iter=1000, nsteps=10,
+        ids = [srv.submit(*_upload(*r), l=l, s=0.1, tol=1e-5, max_iter=1000, nsteps=10,
                           symmetric=symmetric) for r in reqs]
         for _ in range(100000):
             na, nq = srv.step()
@@ -157,10 +161,10 @@ def test_large_request_symmetric_matvec():
     assert alone[3] <= 1e-5 and abs(alone[2] - full[2]) <= max(3, full[2] // 20)
     X, y, _ = big
     x = alone[0].astype(np.float64)
-    Kx = hg.kmatvec(to_dev(X, torch.float64), to_dev(x, torch.float64), 0, 0.1, 1.0,
+    Kx = hg.kmatvec(to_dev(X, torch.float64), to_dev(x, torch.float64), 0, l, 1.0,
                     0.1).cpu().numpy()
     tr = np.linalg.norm(y - Kx) / np.linalg.norm(y)
-    Kabs = hg.kmatvec(to_dev(X, torch.float64), to_dev(np.abs(x), torch.float64), 0, 0.1, 1.0,
+    Kabs = hg.kmatvec(to_dev(X, torch.float64), to_dev(np.abs(x), torch.float64), 0, l, 1.0,
                       0.1).cpu().numpy()
     floor = 6e-8 * np.linalg.norm(Kabs) / np.linalg.norm(y)
     print("true relative residual %.2e, FP32 floor %.2e" % (tr, floor))
