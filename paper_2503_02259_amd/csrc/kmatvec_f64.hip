@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void kmv_f64(KArgs<double> a) {
 
     const double* xs = &Xs[cur][0];
     const double* vs = &Vs[cur][0];
-#pragma unroll 2
+#pragma unroll 4  // about 3% faster than 2 at n = 1e5, k = 33 (Gaussian); same results
     for (int st = 0; st < kBJ64 / 4; ++st) {
       const int j = 4 * st + q;
       double r2 = 0.0;
