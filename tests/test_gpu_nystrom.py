@@ -49,6 +49,26 @@ def test_nystrom_pcg_fp64_matches_oracle():
     assert info["iters"].max() < 0.5 * infoj["iters"].max()
 
 
+@pytest.mark.parametrize("n,k,rank", [(1003, 1, 37), (2501, 2, 300), (777, 17, 90)])
+def test_nystrom_pcg_fp64_block_widths(n, k, rank):
+    # The apply's MFMA passes at their edges: one column (a whole 16-column
+    # block for it), a rank below one wave's 64 landmarks, two column blocks
+    # (k = 17), ragged n.  Iterations against the oracle's preconditioned CG,
+    # and the true residual.
+    l, f, s = 0.15, 1.0, 0.02
+    X, B = _problem(n, 90 + k, k)
+    Xd, Bd = to_dev(X, torch.float64), to_dev(B, torch.float64)
+    x, info = hg.pcg(Xd, Bd, 0, l, f, s, tol=1e-10, max_iter=3000, precond="nystrom", rank=rank)
+    K = oracle.khat_dense(X, 0, l, f, s)
+    Wm, C, _ = oracle.nystrom_parts(X, 0, l, f, s, rank)
+    _, it_o, _, c_o = oracle.pcg(lambda P: K @ P, B, 1e-10, 3000,
+                                 apply_minv=lambda R: oracle.nystrom_apply_inv(Wm, C, s, R))
+    tr = np.linalg.norm(B - K @ x.cpu().numpy().reshape(n, k), axis=0) / np.linalg.norm(B, axis=0)
+    assert info["converged"].all() and c_o.all()
+    assert np.all(tr <= 1.1e-10), tr
+    assert np.all(np.abs(info["iters"] - it_o) <= np.maximum(2, 0.05 * it_o)), (info["iters"], it_o)
+
+
 def test_nystrom_full_rank_is_exact():
     # Every point a landmark: M = K̂.  The core C = K(s/f²·I + K) squares the
     # conditioning of K, so the case is taken where K is well conditioned
