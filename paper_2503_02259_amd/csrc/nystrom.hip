@@ -23,6 +23,7 @@
 // per PCG iteration): T = LᵀR by row chunks with FP64 partial sums added in
 // chunk order, u = C⁻¹T, Z = (R − L·u)/s.  Everything is deterministic.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -511,22 +512,71 @@ void host_parallel_for(int n, F f) {
   for (auto& th : team) th.join();
 }
 
-bool chol_lower(const std::vector<double>& A, int r, std::vector<double>& L) {
-  L.assign((size_t)r * r, 0.0);
-  for (int i = 0; i < r; ++i) {
-    const double* li = &L[(size_t)i * r];
-    for (int j = 0; j <= i; ++j) {
-      const double* lj = &L[(size_t)j * r];
-      const double s = A[(size_t)i * r + j] - dot8(li, lj, j);
-      if (i == j) {
-        if (!(s > 0.0)) return false;
-        L[(size_t)i * r + i] = std::sqrt(s);
-      } else {
-        L[(size_t)i * r + j] = s / lj[j];
-      }
+// Sense-reversing spin barrier for a team of host threads.
+class SpinBarrier {
+ public:
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    const int gen = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.store(gen + 1, std::memory_order_release);
+    } else {
+      while (gen_.load(std::memory_order_acquire) == gen) std::this_thread::yield();
     }
   }
-  return true;
+
+ private:
+  const int n_;
+  std::atomic<int> count_{0};
+  std::atomic<int> gen_{0};
+};
+
+// Column j of the factor: L[i][j] = (A[i][j] − Σ_{k<j} L[i][k]·L[j][k]) / L[j][j]
+// for i > j, with L[j][j] = √(A[j][j] − Σ_{k<j} L[j][k]²).  Every entry is
+// computed by the same dot8 whether the columns' rows are shared out among
+// threads or not, so the factor does not depend on the thread count.
+bool chol_lower(const std::vector<double>& A, int r, std::vector<double>& L) {
+  L.assign((size_t)r * r, 0.0);
+  const int nt = r < 512 ? 1 : (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  auto diag = [&](int j) { return A[(size_t)j * r + j] - dot8(&L[(size_t)j * r], &L[(size_t)j * r], j); };
+  if (nt == 1) {
+    for (int j = 0; j < r; ++j) {
+      const double s = diag(j);
+      if (!(s > 0.0)) return false;
+      const double d = std::sqrt(s);
+      L[(size_t)j * r + j] = d;
+      const double* lj = &L[(size_t)j * r];
+      for (int i = j + 1; i < r; ++i)
+        L[(size_t)i * r + j] = (A[(size_t)i * r + j] - dot8(&L[(size_t)i * r], lj, j)) / d;
+    }
+    return true;
+  }
+  // One barrier per column: each thread forms the diagonal itself (the same
+  // value in every thread), thread 0 stores it, and the rows below are
+  // shared out in a fixed interleave.
+  SpinBarrier bar(nt);
+  std::atomic<bool> ok{true};
+  auto work = [&](int t) {
+    for (int j = 0; j < r; ++j) {
+      const double s = diag(j);
+      if (!(s > 0.0)) {
+        if (t == 0) ok.store(false);
+        return;  // every thread sees the same s and leaves at the same column
+      }
+      const double d = std::sqrt(s);
+      if (t == 0) L[(size_t)j * r + j] = d;
+      const double* lj = &L[(size_t)j * r];
+      for (int i = j + 1 + t; i < r; i += nt)
+        L[(size_t)i * r + j] = (A[(size_t)i * r + j] - dot8(&L[(size_t)i * r], lj, j)) / d;
+      bar.wait();
+    }
+  };
+  std::vector<std::thread> team;
+  for (int t = 1; t < nt; ++t) team.emplace_back(work, t);
+  work(0);
+  for (auto& th : team) th.join();
+  return ok.load();
 }
 
 // Inverse of the lower-triangular L, returned transposed: Mt[j][i] =
