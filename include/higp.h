@@ -366,6 +366,15 @@ const char* higp_last_error(void);
 /* ABI version: major·10000 + minor·100 + patch.                            */
 int higp_version(void);
 
+/* Test hook for failure handling (not part of any computation): the next
+ * `count` scratch allocations made by the library in this process (any
+ * thread, any call) fail as if the device were out of memory, so that the
+ * calls making them return HIGP_ERR_OOM having launched nothing that
+ * depends on the missing memory and leaving no state behind.  count = 0
+ * disarms the hook.  Returns HIGP_ERR_INVALID_ARG for count < 0.  No GPU
+ * needed.                                                                   */
+int higp_debug_fail_allocs(int32_t count);
+
 #ifdef __cplusplus
 }
 #endif

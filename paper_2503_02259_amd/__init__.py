@@ -12,7 +12,7 @@ def __getattr__(name):
     # Import the torch-facing API lazily so that `workloads` and the build
     # script can be used without importing torch.
     if name in ("kmatvec", "kmatvec_grad", "kmatvec_cross", "pcg", "slq_logdet", "tridiag_eig",
-                "problem", "coldot", "nlml", "gpr_predict", "fps_landmarks"):
+                "problem", "coldot", "nlml", "gpr_predict", "fps_landmarks", "debug_fail_allocs"):
         from . import api
         return getattr(api, name)
     if name in ("KMatVecFn", "GPLossFn", "GPRModel", "train_gpr"):

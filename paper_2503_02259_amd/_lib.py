@@ -28,7 +28,7 @@ EXPORTS = ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_pcg"
            "higp_slq_logdet", "higp_coldot", "higp_nlml", "higp_gpr_predict",
            "higp_fps_landmarks", "higp_request_footprint", "higp_server_create", "higp_server_submit",
            "higp_server_step", "higp_server_status", "higp_server_destroy", "higp_tridiag_eig",
-           "higp_error_string", "higp_last_error", "higp_version")
+           "higp_error_string", "higp_last_error", "higp_version", "higp_debug_fail_allocs")
 
 HIGP_REQ_QUEUED, HIGP_REQ_ACTIVE, HIGP_REQ_DONE, HIGP_REQ_FAILED = 0, 1, 2, 3
 
@@ -132,6 +132,7 @@ def lib():
         L.higp_last_error.argtypes = []
         L.higp_last_error.restype = ctypes.c_char_p
         L.higp_version.argtypes = []
+        L.higp_debug_fail_allocs.argtypes = [i32]
         for name in ("higp_kmatvec", "higp_kmatvec_grad", "higp_kmatvec_cross", "higp_gpr_predict",
                      "higp_fps_landmarks",
                      "higp_pcg", "higp_slq_logdet",

@@ -281,3 +281,9 @@ def fps_landmarks(X, rank, stream=None):
                                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                             _stream(stream, X.device)))
     return idx
+
+
+def debug_fail_allocs(count):
+    """Test hook: the library's next ``count`` scratch allocations fail with
+    HIGP_ERR_OOM (0 disarms it)."""
+    _lib.check(_lib.lib().higp_debug_fail_allocs(int(count)))

@@ -23,6 +23,7 @@ int host_coldot(int64_t n, int k, const void* A, int ta, const void* B, int tb, 
 namespace {
 thread_local char g_msg[512] = "";
 std::atomic<bool> g_pool_ready[64];  // per device: release threshold raised
+std::atomic<int> g_fail_allocs{0};   // scratch allocations the test hook makes fail
 }  // namespace
 
 int set_error(int code, const char* fmt, ...) {
@@ -79,6 +80,12 @@ int scratch_alloc(void** ptr, size_t bytes, hipStream_t st) {
     }
     g_pool_ready[dev].store(true, std::memory_order_release);
   }
+  // Allocations the test hook makes fail (higp_debug_fail_allocs).
+  for (int c = g_fail_allocs.load(); c > 0;)
+    if (g_fail_allocs.compare_exchange_weak(c, c - 1)) {
+      *ptr = nullptr;
+      return set_error(HIGP_ERR_OOM, "scratch allocation of %zu bytes failed (injected)", bytes);
+    }
   hipError_t e = hipMallocAsync(ptr, bytes ? bytes : 256, st);
   if (e != hipSuccess) {
     *ptr = nullptr;
@@ -115,6 +122,12 @@ using namespace higp;
 extern "C" {
 
 int higp_version(void) { return 200; }
+
+int higp_debug_fail_allocs(int32_t count) {
+  if (count < 0) return set_error(HIGP_ERR_INVALID_ARG, "count must be >= 0");
+  g_fail_allocs.store(count);
+  return HIGP_OK;
+}
 
 const char* higp_error_string(int code) {
   switch (code) {

@@ -245,3 +245,9 @@ def test_gpr_predict_validation():
     pb = _prob(prec=_lib.BF16)
     assert L.higp_gpr_predict(ctypes.byref(pb), y, 5, xq, ctypes.byref(o), mean, None, None,
                               None) == _lib.HIGP_ERR_UNSUPPORTED
+
+
+def test_debug_fail_allocs_rejects_negative_count():
+    L = _lib.lib()
+    assert L.higp_debug_fail_allocs(-1) == _lib.HIGP_ERR_INVALID_ARG
+    assert L.higp_debug_fail_allocs(0) == _lib.HIGP_OK
